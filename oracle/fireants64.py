@@ -1,0 +1,457 @@
+"""FP64 CPU oracle of the FireANTs dense matching step (arXiv 2404.01249).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the HIP library (no kernels, headers, tables or helpers); both sides take their
+inputs from the seeded generators in ``paper_2404_01249_amd.synth``.
+
+Everything here is plain NumPy in float64, written from the paper's statement
+of the method and in its order:
+
+* Algorithm 1 ("FireANTs"): levels -> iterations -> {cost, Gateaux gradient,
+  optimizer state update, retraction by composition} -> upsample.
+* Section 4.4.2 (Jacobian-free Eulerian descent): the descent direction is the
+  Gateaux derivative of the cost with respect to the warp.
+* Section 4.4, "Adaptive optimization on diffeomorphisms": Adam runs on the
+  sequence of directions, which all live in the tangent space at identity.
+* Appendix E (limitations of stationary velocity fields): the step scale is
+  eta / LP(v), with LP(v) bounded by 2 sup |v| / |dx|.
+* Section 4.5 (interpolation strategies): multi-scale pyramid, warp and Adam
+  state carried to the next level by trilinear (not cubic) upsampling.
+* Equation (image-reg): L = C(I, I' o phi) + R(phi), with the pushforward
+  image I'(phi(x)) of Section 4.4.3 ("Alternative formulations").
+
+Where the paper is silent the following readings are used (each is repeated at
+the function that applies it):
+
+* LNCC (named, never written out, in the problem statement and in the
+  hyperparameter study): squared local correlation cross^2 / (var_I var_J + eps)
+  over a w^3 window clipped to the domain, divided by the true voxel count;
+  the cost is minus its mean.  eps regularises the sum-form variances.
+* Values outside the domain are zero, per sample corner, for images and for
+  the displacement (the subgroup of Eq. (flowdiff) extends u by zero outside
+  the domain).
+* Voxel-index coordinates; the displacement d is in voxels; phi = id + d.
+* Gaussian smoothing: sampled kernel normalised to sum 1, radius ceil(3 sigma),
+  replicate boundary; sigma is in voxels of the current level.
+* Order inside one iteration: gradient -> Adam -> smooth (sigma_grad) ->
+  normalise -> compose -> smooth (sigma_warp).
+* Step normalisation follows the printed inequality with dx = 1 voxel:
+  u = -eta * s / (2 max|s|), so no voxel moves more than eta/2.
+* Adam: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias corrected, the step count
+  carries across levels.
+* Pyramid: level size round(n / s); image = trilinear resample, at
+  corner-aligned positions, of the image blurred with sigma = s/2 (no blur at
+  s = 1).  Displacements are multiplied by (n_f - 1)/(n_c - 1) per axis on
+  upsampling; the Adam moments are upsampled unscaled.
+
+Parity status of every function is pinned in tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Params", "trilinear", "trilinear_dpos", "identity_grid", "warp_image",
+    "box_sum", "window_count",
+    "lncc_forward", "lncc_grad_warped", "gateaux_gradient", "adam_update",
+    "gaussian_weights", "gaussian_smooth", "normalise_step", "compose",
+    "iterate", "level_shape", "downsample_image", "upsample_state", "register",
+    "warp_labels_nearest", "dice", "jacobian_det", "singular_fraction",
+]
+
+
+@dataclass
+class Params:
+    """Hyperparameters of one registration (Algorithm 1 inputs plus the
+    smoothing widths of the hyperparameter study)."""
+    eta: float = 0.5
+    sigma_grad: float = 1.0
+    sigma_warp: float = 0.5
+    window: int = 5
+    cc_eps: float = 1e-5
+    beta1: float = 0.9
+    beta2: float = 0.999
+    adam_eps: float = 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Trilinear sampling (the warp I o phi of Algorithm 1, and the composition)
+# ---------------------------------------------------------------------------
+
+def _corner_values(f, i0, i1, i2):
+    n0, n1, n2 = f.shape
+    ok = (i0 >= 0) & (i0 < n0) & (i1 >= 0) & (i1 < n1) & (i2 >= 0) & (i2 < n2)
+    v = f[np.clip(i0, 0, n0 - 1), np.clip(i1, 0, n1 - 1), np.clip(i2, 0, n2 - 1)]
+    return np.where(ok, v, 0.0)
+
+
+def trilinear(f, p):
+    """T(f, p): trilinear interpolation of volume ``f`` at positions ``p``.
+
+    ``p`` has shape (3, ...) in voxel-index coordinates.  Each of the 8 cell
+    corners outside the grid contributes zero (zero extension outside the
+    domain, as for the subgroup of Eq. (flowdiff)).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    q = np.floor(p)
+    t = p - q
+    q = q.astype(np.int64)
+    out = np.zeros(p.shape[1:])
+    for b0 in (0, 1):
+        w0 = t[0] if b0 else 1.0 - t[0]
+        for b1 in (0, 1):
+            w1 = t[1] if b1 else 1.0 - t[1]
+            for b2 in (0, 1):
+                w2 = t[2] if b2 else 1.0 - t[2]
+                out += w0 * w1 * w2 * _corner_values(f, q[0] + b0, q[1] + b1, q[2] + b2)
+    return out
+
+
+def trilinear_dpos(f, p):
+    """dT(f, p)/dp_a for a = 0, 1, 2 (shape (3, ...)).
+
+    The same corner sum as :func:`trilinear` with the weight along axis ``a``
+    replaced by -1 / +1.  At an integer coordinate this is the derivative from
+    the right (the cell is chosen by floor(p)).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    q = np.floor(p)
+    t = p - q
+    q = q.astype(np.int64)
+    out = np.zeros((3,) + p.shape[1:])
+    for b0 in (0, 1):
+        for b1 in (0, 1):
+            for b2 in (0, 1):
+                v = _corner_values(f, q[0] + b0, q[1] + b1, q[2] + b2)
+                w = [(t[k] if b else 1.0 - t[k]) for k, b in enumerate((b0, b1, b2))]
+                dw = [(1.0 if b else -1.0) for b in (b0, b1, b2)]
+                out[0] += dw[0] * w[1] * w[2] * v
+                out[1] += w[0] * dw[1] * w[2] * v
+                out[2] += w[0] * w[1] * dw[2] * v
+    return out
+
+
+def identity_grid(shape):
+    return np.indices(shape, dtype=np.float64)
+
+
+def warp_image(img, d):
+    """J(x) = I(x + d(x)) -- the pushforward image of Section 4.4.3."""
+    return trilinear(img, identity_grid(img.shape) + d)
+
+
+# ---------------------------------------------------------------------------
+# LNCC (the cost C of Eq. (image-reg); window size is its hyperparameter)
+# ---------------------------------------------------------------------------
+
+def box_sum(f, r):
+    """Sum of ``f`` over the window {y in grid : |y_a - x_a| <= r for all a}.
+
+    The window is clipped to the grid.  Written as a sum over shifted copies,
+    one axis at a time (the window is a product of intervals).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    out = f
+    for ax in range(f.ndim):
+        n = f.shape[ax]
+        acc = np.zeros_like(out)
+        for k in range(-r, r + 1):
+            if abs(k) >= n:
+                continue
+            dst = [slice(None)] * f.ndim
+            src = [slice(None)] * f.ndim
+            if k >= 0:   # acc[i] += out[i + k] for i + k < n
+                dst[ax], src[ax] = slice(0, n - k), slice(k, n)
+            else:
+                dst[ax], src[ax] = slice(-k, n), slice(0, n + k)
+            acc[tuple(dst)] += out[tuple(src)]
+        out = acc
+    return out
+
+
+def window_count(shape, r):
+    """n(x) = number of grid voxels in the clipped window at x."""
+    return box_sum(np.ones(shape), r)
+
+
+def lncc_forward(I, J, window, eps):
+    """Local squared correlation over clipped w^3 windows.
+
+    Returns (cc, L, parts) with cc(x) = cross^2 / (vI vJ + eps) and
+    L = -mean(cc).  cross, vI, vJ are the window sums of (I - muI)(J - muJ),
+    (I - muI)^2 and (J - muJ)^2 (sum form, not divided by the count); eps is
+    added to their product.  Where the denominator is 0 (eps = 0 and a flat
+    window) cc is defined as 0.
+    """
+    I = np.asarray(I, np.float64)
+    J = np.asarray(J, np.float64)
+    r = window // 2
+    n = window_count(I.shape, r)
+    SI, SJ = box_sum(I, r), box_sum(J, r)
+    SII, SJJ, SIJ = box_sum(I * I, r), box_sum(J * J, r), box_sum(I * J, r)
+    muI, muJ = SI / n, SJ / n
+    cross = SIJ - muI * SJ
+    vI = SII - muI * SI
+    vJ = SJJ - muJ * SJ
+    D = vI * vJ + eps
+    ok = D != 0
+    Ds = np.where(ok, D, 1.0)
+    cc = np.where(ok, cross * cross / Ds, 0.0)
+    L = -cc.mean()
+    parts = dict(n=n, muI=muI, muJ=muJ, cross=cross, vI=vI, vJ=vJ, D=D, ok=ok)
+    return cc, L, parts
+
+
+def lncc_grad_warped(I, J, window, eps):
+    """dL/dJ(y) for L = -mean(cc) (adjoint of the window sums).
+
+    With A = 2 cross/D, B = -2 cross^2 vI / D^2 and C = A muI + B muJ per
+    window centre x, and S~ the same clipped box sum taken over centres:
+        dL/dJ(y) = -(1/N) [ I(y) S~A(y) + J(y) S~B(y) - S~C(y) ].
+    (d cross / dJ(y) = I(y) - muI and d vJ / dJ(y) = 2 (J(y) - muJ); muI and
+    vI do not depend on J.)
+    """
+    I = np.asarray(I, np.float64)
+    J = np.asarray(J, np.float64)
+    r = window // 2
+    _, L, P = lncc_forward(I, J, window, eps)
+    ok = P["ok"]
+    Ds = np.where(ok, P["D"], 1.0)
+    A = np.where(ok, 2.0 * P["cross"] / Ds, 0.0)
+    B = np.where(ok, -2.0 * P["cross"] ** 2 * P["vI"] / (Ds * Ds), 0.0)
+    C = A * P["muI"] + B * P["muJ"]
+    N = I.size
+    dJ = -(I * box_sum(A, r) + J * box_sum(B, r) - box_sum(C, r)) / N
+    return dJ, L
+
+
+def gateaux_gradient(fixed, moving, d, window, eps):
+    """Gateaux derivative dU/dphi of U = C(I_f, I_m o phi) at phi = id + d
+    (the Jacobian-free Eulerian descent direction of Section 4.4.2, up to sign).
+
+    g_a(x) = dL/dJ(x) * dT(I_m, x + d(x))/dp_a.  Only the warped image depends
+    on phi; the moving image itself is not differentiated.  Returns (g, L).
+    """
+    p = identity_grid(fixed.shape) + np.asarray(d, np.float64)
+    J = trilinear(moving, p)
+    dJ, L = lncc_grad_warped(fixed, J, window, eps)
+    return dJ[None] * trilinear_dpos(moving, p), L
+
+
+# ---------------------------------------------------------------------------
+# Adam on the tangent space at identity (Section 4.4)
+# ---------------------------------------------------------------------------
+
+def adam_update(g, m, v, t, beta1, beta2, eps):
+    """One Adam step (Kingma & Ba) at step count ``t`` (already incremented).
+
+    Returns (a, m, v) with a = mhat / (sqrt(vhat) + eps)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Gaussian smoothing (sigma_grad, sigma_warp of the hyperparameter study)
+# ---------------------------------------------------------------------------
+
+def gaussian_weights(sigma):
+    """Sampled Gaussian, radius ceil(3 sigma), normalised to sum 1.
+
+    ``sigma`` is first rounded to float32, as the library receives it."""
+    s = float(np.float32(sigma))
+    R = int(math.ceil(3.0 * s))
+    k = np.arange(-R, R + 1, dtype=np.float64)
+    w = np.exp(-(k * k) / (2.0 * s * s))
+    return w / w.sum()
+
+
+def gaussian_smooth(f, sigma):
+    """Separable Gaussian along each spatial axis of ``f`` (last three axes),
+    replicate boundary (index clamped to the grid).  sigma <= 0: identity."""
+    f = np.asarray(f, np.float64)
+    if not sigma > 0:
+        return f.copy()
+    w = gaussian_weights(sigma)
+    R = len(w) // 2
+    out = f
+    nd = f.ndim
+    for ax in range(nd - 3, nd):
+        n = f.shape[ax]
+        acc = np.zeros_like(out)
+        for j, k in enumerate(range(-R, R + 1)):
+            idx = np.clip(np.arange(n) + k, 0, n - 1)
+            acc += w[j] * np.take(out, idx, axis=ax)
+        out = acc
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Step scale (Appendix E) and retraction by composition (Algorithm 1)
+# ---------------------------------------------------------------------------
+
+def normalise_step(s, eta):
+    """u = -eta s / (2 M), M = max_x |s(x)|_2; u = 0 when M = 0.
+
+    The scale eps_t = eta / LP(v) with the bound LP(v) <= 2 sup |v| / |dx|,
+    dx = 1 voxel.  Returns (u, M)."""
+    M = float(np.sqrt((s * s).sum(0)).max())
+    if M > 0:
+        return (-eta / (2.0 * M)) * s, M
+    return np.zeros_like(s), M
+
+
+def compose(d, u):
+    """Displacement of phi o (id + u) for phi = id + d:
+        d'(x) = u(x) + d(x + u(x)),
+    with d sampled trilinearly per component and zero outside the grid."""
+    p = identity_grid(d.shape[1:]) + u
+    return u + np.stack([trilinear(d[c], p) for c in range(3)])
+
+
+def iterate(fixed, moving, d, m, v, t, P: Params):
+    """One iteration of Algorithm 1 at one level.
+
+    ``t`` is the Adam step count after increment.  Returns
+    (d_new, m, v, L, extras) where extras holds the intermediates."""
+    g, L = gateaux_gradient(fixed, moving, d, P.window, P.cc_eps)
+    a, m, v = adam_update(g, m, v, t, P.beta1, P.beta2, P.adam_eps)
+    s = gaussian_smooth(a, P.sigma_grad)
+    u, M = normalise_step(s, P.eta)
+    d1 = compose(d, u)
+    d_new = gaussian_smooth(d1, P.sigma_warp)
+    return d_new, m, v, L, dict(g=g, a=a, s=s, M=M, u=u, d_composed=d1)
+
+
+# ---------------------------------------------------------------------------
+# Multi-scale pyramid and level transitions (Section 4.5)
+# ---------------------------------------------------------------------------
+
+def level_shape(shape, scale):
+    """Grid size at downsampling factor ``scale``: max(1, floor(n/s + 1/2))."""
+    s = float(np.float32(scale))
+    return tuple(max(1, int(math.floor(n / s + 0.5))) for n in shape)
+
+
+def _aligned_positions(n_from, n_to):
+    """Corner-aligned sample positions of an n_to grid inside an n_from grid,
+    per axis: i (n_from - 1) / (n_to - 1)."""
+    out = []
+    for a in range(3):
+        i = np.arange(n_to[a], dtype=np.float64)
+        if n_to[a] > 1:
+            out.append(i * (n_from[a] - 1) / (n_to[a] - 1))
+        else:
+            out.append(np.zeros(1))
+    return np.stack(np.meshgrid(*out, indexing="ij"))
+
+
+def downsample_image(img, scale):
+    """Image at downsampling factor ``scale``: blur with sigma = scale/2, then
+    trilinear resampling at corner-aligned positions.  Identity at scale 1."""
+    img = np.asarray(img, np.float64)
+    shp = level_shape(img.shape, scale)
+    if float(np.float32(scale)) == 1.0 and shp == img.shape:
+        return img.copy()
+    blurred = gaussian_smooth(img, float(np.float32(scale)) / 2.0)
+    return trilinear(blurred, _aligned_positions(img.shape, shp))
+
+
+def upsample_state(d, m, v, shape_f):
+    """Carry (d, m, v) from a coarse grid to ``shape_f`` by trilinear
+    interpolation at corner-aligned positions.  d_a is multiplied by
+    rho_a = (nf_a - 1)/(nc_a - 1) (voxel units change with the grid); the Adam
+    moments are interpolated unscaled."""
+    shape_c = d.shape[1:]
+    pos = _aligned_positions(shape_c, shape_f)
+    rho = [((shape_f[a] - 1) / (shape_c[a] - 1)) if shape_c[a] > 1 else 1.0 for a in range(3)]
+    d2 = np.stack([rho[c] * trilinear(d[c], pos) for c in range(3)])
+    m2 = np.stack([trilinear(m[c], pos) for c in range(3)])
+    v2 = np.stack([trilinear(v[c], pos) for c in range(3)])
+    return d2, m2, v2
+
+
+def register(fixed, moving, scales, iters, P: Params, callback=None):
+    """Algorithm 1 with use_jac off (as in all of the paper's experiments).
+
+    Returns (d, losses, t): the displacement at the finest level, one loss per
+    iteration (the cost before that iteration's update) and the final step
+    count.  ``callback(level, i, d, m, v, L, extras)`` is called after each
+    iteration when given."""
+    fixed = np.asarray(fixed, np.float64)
+    moving = np.asarray(moving, np.float64)
+    d = m = v = None
+    t = 0
+    losses = []
+    for lvl, (s, T) in enumerate(zip(scales, iters)):
+        If = downsample_image(fixed, s)
+        Im = downsample_image(moving, s)
+        if d is None:
+            d = np.zeros((3,) + If.shape)
+            m = np.zeros_like(d)
+            v = np.zeros_like(d)
+        else:
+            d, m, v = upsample_state(d, m, v, If.shape)
+        for i in range(int(T)):
+            t += 1
+            d, m, v, L, ex = iterate(If, Im, d, m, v, t, P)
+            losses.append(L)
+            if callback is not None:
+                callback(lvl, i, d, m, v, L, ex)
+    return d, losses, t
+
+
+# ---------------------------------------------------------------------------
+# Evaluation: label overlap and invertibility diagnostics
+# ---------------------------------------------------------------------------
+
+def warp_labels_nearest(labels, d):
+    """labels(round(x + d(x))), rounding half up; -1 where the rounded
+    position leaves the grid."""
+    p = np.floor(identity_grid(labels.shape) + d + 0.5).astype(np.int64)
+    ok = np.ones(labels.shape, bool)
+    for a in range(3):
+        ok &= (p[a] >= 0) & (p[a] < labels.shape[a])
+    pc = [np.clip(p[a], 0, labels.shape[a] - 1) for a in range(3)]
+    return np.where(ok, labels[pc[0], pc[1], pc[2]], -1).astype(np.int64)
+
+
+def dice(a, b, classes):
+    """Mean over ``classes`` of 2|A_r and B_r| / (|A_r| + |B_r|)."""
+    out = []
+    for r in classes:
+        A, B = a == r, b == r
+        den = A.sum() + B.sum()
+        out.append(2.0 * (A & B).sum() / den if den else 1.0)
+    return float(np.mean(out))
+
+
+def jacobian_det(d):
+    """det(I + grad d) at interior voxels by central differences
+    (shape (n0-2, n1-2, n2-2))."""
+    d = np.asarray(d, np.float64)
+    J = np.empty((3, 3) + tuple(n - 2 for n in d.shape[1:]))
+    for c in range(3):
+        for a in range(3):
+            hi = [slice(1, -1)] * 3
+            lo = [slice(1, -1)] * 3
+            hi[a] = slice(2, None)
+            lo[a] = slice(0, -2)
+            J[c, a] = 0.5 * (d[c][tuple(hi)] - d[c][tuple(lo)]) + (1.0 if c == a else 0.0)
+    return (J[0, 0] * (J[1, 1] * J[2, 2] - J[1, 2] * J[2, 1])
+            - J[0, 1] * (J[1, 0] * J[2, 2] - J[1, 2] * J[2, 0])
+            + J[0, 2] * (J[1, 0] * J[2, 1] - J[1, 1] * J[2, 0]))
+
+
+def singular_fraction(d):
+    """Fraction of interior voxels with det(I + grad d) <= 0."""
+    det = jacobian_det(d)
+    return float((det <= 0).mean())
