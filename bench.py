@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the FireANTs dense matching step on one MI355X.
+
+One *step* is one whole registration of the 160x192x224 tissue pair:
+building the three-level pyramid (4x, 2x, 1x) and running 200/100/50
+iterations of Algorithm 1 (warp, LNCC, adjoint, Adam, smoothing, composition,
+level upsampling).  The metric is voxel-iterations per second,
+sum_l N_l T_l / (seconds per step), with the input volumes already resident
+in device memory when timing starts.
+
+Prints one JSON line.  Besides the headline value it reports
+* ``roofline``: the dominant kernel's algorithmic HBM bytes per launch over
+  its average launch time, measured with HIP events on the pair's stream
+  during the timed steps, against the 8 TB/s HBM peak;
+* ``plain_torch``: the same algorithm written with stock PyTorch operators
+  (grid_sample, conv3d, autograd, elementwise Adam) on the same GPU;
+* ``cpu_baseline``: the FP64 NumPy oracle timed on the host, on a bounded
+  sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/sec @160×192×224 fused vs plain per-op GPU, same accuracy"
+HBM_PEAK_GBS = 8000.0
+GRAD_BYTES_PER_VOXEL = 80   # reads I_f, I_m, d(3), m(3), v(3); writes m(3), v(3), a(3); fp32
+
+
+def level_voxels(shape, scales, iters):
+    out = []
+    for s, t in zip(scales, iters):
+        n = 1
+        for dim in shape:
+            n *= max(1, int(dim / float(s) + 0.5))
+        out.append((n, t))
+    return out
+
+
+def run_fused(p, steps, warmup, params):
+    import torch
+
+    from paper_2404_01249_amd import Pair, fa
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    stream = torch.cuda.current_stream()
+    pr = Pair(fixed, moving, stream=stream, **params)
+    for _ in range(warmup):
+        pr.set_schedule(p.scales, p.iters)
+        pr.run()
+    torch.cuda.synchronize()
+    fa.fa_pair_profile(pr.handle, True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        pr.set_schedule(p.scales, p.iters)
+        pr.run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / steps
+    prof = {}
+    for lvl in range(len(p.scales)):
+        prof[lvl] = [fa.fa_pair_get_profile(pr.handle, lvl, k) for k in range(4)]
+    fa.fa_pair_profile(pr.handle, False)
+    loss = pr.loss_history()
+    pr.close()
+    return ms, wall / steps, prof, loss
+
+
+def run_plain(p, steps, warmup, params):
+    import torch
+
+    import bench_plain
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    for _ in range(warmup):
+        bench_plain.register(fixed, moving, p.scales, p.iters, **params)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        d, losses = bench_plain.register(fixed, moving, p.scales, p.iters, **params)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps, losses
+
+
+def cpu_baseline(p, params, budget_s=20.0):
+    """The FP64 oracle on a bounded sample: iterations at the finest level
+    from the identity state until ~budget_s of CPU time is spent."""
+    import numpy as np
+
+    import oracle as O
+    P = O.Params(eta=params["eta"], sigma_grad=params["sigma_grad"], sigma_warp=params["sigma_warp"],
+                 window=params["window"])
+    f = p.fixed.astype(np.float64)
+    m_ = p.moving.astype(np.float64)
+    d = np.zeros((3,) + f.shape)
+    m = np.zeros_like(d)
+    v = np.zeros_like(d)
+    n_it = 0
+    t0 = time.process_time()
+    w0 = time.perf_counter()
+    while True:
+        n_it += 1
+        d, m, v, L, _ = O.iterate(f, m_, d, m, v, n_it, P)
+        if time.process_time() - t0 >= budget_s or n_it >= 50:
+            break
+    cpu = time.process_time() - t0
+    wall = time.perf_counter() - w0
+    rate = f.size * n_it / wall
+    return {"value": rate, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_it} iteration(s) of Algorithm 1 at the finest 160x192x224 level from the "
+                      f"identity state, FP64 NumPy, single thread ({wall:.1f} s wall, {cpu:.1f} s CPU)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tissue160")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain PyTorch comparison")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the dense matching step of one registration is not "
+              "sharded across GPUs in this build (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+
+    import torch
+
+    from paper_2404_01249_amd import synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    p = synth.load(args.workload)
+    params = dict(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=p.window)
+    lv = level_voxels(p.fixed.shape, p.scales, p.iters)
+    vox_iters = sum(n * t for n, t in lv)
+
+    ms, wall_ms, prof, loss = run_fused(p, args.steps, args.warmup, params)
+    value = vox_iters / (ms / 1e3)
+
+    # dominant kernel: the fused gradient kernel at the finest level
+    fin = len(p.scales) - 1
+    g_ms, g_n = prof[fin][0]
+    per_launch_ms = g_ms / max(g_n, 1)
+    n_fin = lv[fin][0]
+    achieved = GRAD_BYTES_PER_VOXEL * n_fin / (per_launch_ms / 1e3) / 1e9
+    split = {}
+    names = ["grad_adam", "smooth_maxnorm", "smooth_compose", "smooth_warp"]
+    for lvl, rows in prof.items():
+        split[f"level{lvl}"] = {names[k]: round(rows[k][0] / max(rows[k][1], 1) * 1e3, 2) for k in range(4)}
+    iter_ms_fin = sum(r[0] for r in prof[fin]) / max(prof[fin][0][1], 1)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxel-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{p.name}: {'x'.join(map(str, p.fixed.shape))} fp32 pair, "
+                               f"scales {p.scales} at {p.iters} iterations, LNCC {p.window}^3, "
+                               f"eta 0.5, sigma_grad 1.0, sigma_warp 0.5",
+                   "voxel_iters_per_step": vox_iters, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_grad (warp+LNCC+adjoint+Adam), finest level",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": GRAD_BYTES_PER_VOXEL * n_fin, "avg_launch_us": per_launch_ms * 1e3,
+                     "launches": g_n},
+        "steady_state_finest": {"us_per_iteration": iter_ms_fin * 1e3,
+                                "voxel_iters_per_s": n_fin / (iter_ms_fin / 1e3),
+                                "roofline_frac_80B": GRAD_BYTES_PER_VOXEL * n_fin / (iter_ms_fin / 1e3) / 1e9
+                                / HBM_PEAK_GBS},
+        "kernel_us_by_level": split,
+        "wall_ms_per_step": wall_ms * 1e3,
+        "final_loss": float(loss[-1]) if len(loss) else None,
+    }
+    if not args.no_plain:
+        try:
+            pms, plosses = run_plain(p, args.plain_steps, 0, params)
+            out["plain_torch"] = {"value": vox_iters / (pms / 1e3), "ms_per_step": pms,
+                                  "speedup_fused": pms / ms, "final_loss": float(plosses[-1])}
+        except Exception as e:  # the comparison must not hide the headline line
+            out["plain_torch"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, params, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,67 @@
+/*
+ * fa_inspect.h -- state access and intermediate readback for a registration
+ * pair (include/fa.h).  These calls let a caller check each step of one
+ * iteration of Algorithm 1 on its own, resume from a saved state, or evaluate
+ * the cost and its gradient without stepping.  Same conventions as fa.h.
+ */
+#ifndef FA_INSPECT_H_
+#define FA_INSPECT_H_
+
+#include "fa.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Current level (0-based), iterations completed at that level, and the Adam
+ * step count t (iterations completed since the schedule was set, across
+ * levels).  Any pointer may be NULL.  Host-side only; no synchronisation. */
+fa_status fa_pair_get_progress(fa_pair pair, int* level, int* iter_in_level, int* t_done);
+
+/* Overwrite the optimiser state at the current level: displacement d and the
+ * Adam moments m (EMA of the gradient) and v (EMA of its square), each a
+ * device SoA array [3][n0][n1][n2] of the current level (NULL leaves that
+ * array unchanged), and the Adam step count t_done (>= 0; the next iteration
+ * uses step t_done + 1 in the bias corrections).  The loss history and the
+ * schedule position are not changed.
+ * Section 4.5 keeps m and v at the scale of the warp, so they are set with
+ * it.  Enqueued.  FA_ESTATE before a schedule. */
+fa_status fa_pair_set_state(fa_pair pair, const float* d, const float* m, const float* v, int t_done);
+
+/* Copy d, m, v of the current level into device arrays (NULL skips). Enqueued. */
+fa_status fa_pair_get_state(fa_pair pair, float* d, float* m, float* v);
+
+/* Evaluate, at the current state and level and without changing it, the
+ * cost L = -mean LNCC(I_f, I_m o phi) and its Gateaux derivative dL/dphi
+ * (the Jacobian-free descent direction of Section 4.4.2, up to sign) into
+ * g_dev (device SoA [3][n0][n1][n2]; NULL: loss only).  *loss_host receives L
+ * (may be NULL).  Synchronises the stream when loss_host is given. */
+fa_status fa_pair_eval_gradient(fa_pair pair, float* g_dev, float* loss_host);
+
+/* The Adam direction a = mhat / (sqrt(vhat) + eps) of the last iteration
+ * (device SoA, current level) into dev_out.  Enqueued. */
+fa_status fa_pair_get_direction(fa_pair pair, float* dev_out);
+
+/* M = max_x |G_sigma_grad * a| of the last iteration (the scale of
+ * Appendix E: u = -eta s / (2M)).  Synchronises the stream. */
+fa_status fa_pair_get_step_norm(fa_pair pair, float* m_host);
+
+/* Pyramid image of level `level` (0-based): which = 0 fixed, 1 moving.
+ * dev_out NULL returns only the shape.  Enqueued. */
+fa_status fa_pair_get_level_image(fa_pair pair, int level, int which, float* dev_out, fa_shape* shape);
+
+/* Kernel timing.  While enabled (enable = 1), every iteration records HIP
+ * events on the pair's stream around each of its kernels; kind 0 = gradient
+ * (warp, LNCC, adjoint, Adam), 1 = smoothed-step norm, 2 = composition,
+ * 3 = warp smoothing.  fa_pair_get_profile synchronises the stream and
+ * returns, for level `level` and kernel `kind`, the summed duration in
+ * milliseconds and the number of launches recorded since profiling was last
+ * enabled.  Enabling clears the totals. */
+fa_status fa_pair_profile(fa_pair pair, int enable);
+fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_ms, int* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FA_INSPECT_H_ */

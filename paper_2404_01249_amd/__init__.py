@@ -1,1 +1,120 @@
-"""MI355X-native FireANTs dense matching step (placeholder; binding added below)."""
+"""MI355X-native FireANTs dense matching step (arXiv 2404.01249).
+
+The computation lives in the HIP library ``libfa_mi355x.so`` (C ABI in
+``include/fa.h``); :mod:`paper_2404_01249_amd.fa` binds it with the same
+names, and :class:`Pair` is a convenience wrapper over those calls.  PyTorch
+only provides device memory and streams.
+"""
+from __future__ import annotations
+
+from . import fa
+from .fa import FAError
+
+__all__ = ["Pair", "FAError", "fa"]
+
+
+class Pair:
+    """One registration problem: fixed and moving 3-D float32 GPU tensors.
+
+    >>> p = Pair(fixed, moving, eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5)
+    >>> p.set_schedule([4, 2, 1], [200, 100, 50]); p.run()
+    >>> d = p.field()          # (3, n0, n1, n2) displacement in voxels
+    """
+
+    def __init__(self, fixed, moving, *, eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5,
+                 cc_eps=1e-5, beta1=0.9, beta2=0.999, adam_eps=1e-8, stream=None):
+        import torch
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        p = fa.fa_params_default()
+        p.eta, p.sigma_grad, p.sigma_warp, p.cc_window = eta, sigma_grad, sigma_warp, window
+        p.cc_eps, p.adam_beta1, p.adam_beta2, p.adam_eps = cc_eps, beta1, beta2, adam_eps
+        self.params = p
+        self.shape = tuple(int(s) for s in fixed.shape)
+        self.handle = fa.fa_pair_create(fixed, moving, p, self.stream)
+        self._keep = (fixed, moving)   # alive until the stream has copied them
+        self.total_iters = 0
+
+    # -- Algorithm 1 driver -------------------------------------------------
+    def set_schedule(self, scales, iters):
+        fa.fa_pair_set_schedule(self.handle, scales, iters)
+        self.total_iters = int(sum(iters))
+        self._keep = None if self._keep is None else self._keep
+
+    def step(self, n):
+        return fa.fa_pair_step(self.handle, n)
+
+    def run(self):
+        done, fin = fa.fa_pair_step(self.handle, 1 << 30)
+        return done
+
+    # -- readback ---------------------------------------------------------------
+    def loss_history(self):
+        return fa.fa_pair_get_loss(self.handle, self.total_iters)
+
+    def level_shape(self):
+        return fa.fa_pair_get_field(self.handle, None)[1]
+
+    def field(self, layout=0):
+        lvl, shp = fa.fa_pair_get_field(self.handle, None)
+        shape = (3,) + shp if layout == 0 else shp + (3,)
+        out = self._torch.empty(shape, dtype=self._torch.float32, device="cuda")
+        fa.fa_pair_get_field(self.handle, out, layout)
+        return out
+
+    def warped(self):
+        shp = self.level_shape()
+        out = self._torch.empty(shp, dtype=self._torch.float32, device="cuda")
+        fa.fa_pair_get_warped(self.handle, out)
+        return out
+
+    def progress(self):
+        return fa.fa_pair_get_progress(self.handle)
+
+    def set_state(self, d=None, m=None, v=None, t_done=0):
+        fa.fa_pair_set_state(self.handle, d, m, v, t_done)
+
+    def state(self):
+        shp = self.level_shape()
+        d, m, v = (self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda") for _ in range(3))
+        fa.fa_pair_get_state(self.handle, d, m, v)
+        return d, m, v
+
+    def eval_gradient(self):
+        shp = self.level_shape()
+        g = self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda")
+        loss = fa.fa_pair_eval_gradient(self.handle, g)
+        return g, loss
+
+    def direction(self):
+        shp = self.level_shape()
+        a = self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda")
+        fa.fa_pair_get_direction(self.handle, a)
+        return a
+
+    def step_norm(self):
+        return fa.fa_pair_get_step_norm(self.handle)
+
+    def level_image(self, level, which):
+        shp = fa.fa_pair_get_level_image(self.handle, level, which, None)
+        out = self._torch.empty(shp, dtype=self._torch.float32, device="cuda")
+        fa.fa_pair_get_level_image(self.handle, level, which, out)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fa.fa_pair_destroy(self.handle)
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+// Nothing here is part of the public C ABI (include/fa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fa {
+
+// Per-pair control block in device memory.  Kernels of one iteration read
+// and update it so that a whole iteration can be replayed (for example from a
+// captured graph) without host involvement.
+struct Ctl {
+  int t;                 // Adam step count of the iteration in flight (1-based)
+  int iter;              // schedule iterations completed (index of the next loss)
+  float bc1, bc2;        // 1 - beta1^t, 1 - beta2^t (computed in double)
+  unsigned int mbits;    // bit pattern of M = max |s| (non-negative float)
+  unsigned int ticket;   // completion counter for the last-workgroup epilogue
+  float beta1, beta2;    // copies of the Adam constants for the t update
+  float shift_i, shift_j;  // mean intensities of the fixed and moving inputs; LNCC
+                           // is invariant to a global intensity shift, and
+                           // removing the mean reduces fp32 cancellation in the
+                           // window variances
+};
+
+// Tile geometry of one streaming launch: in-plane tile (TY x TX) along
+// (n1, n2); the workgroup marches along n0 over a chunk of ZC planes.
+struct Tiling {
+  int ty, tx, zc;
+  int tiles_y, tiles_x, chunks;
+  int blocks() const { return tiles_y * tiles_x * chunks; }
+};
+
+// ---- fused gradient (+ Adam) kernel -------------------------------------
+struct GradArgs {
+  const float* fixed;
+  const float* moving;
+  const float* d;        // [3][N]
+  float* m;              // [3][N] (Adam mode)
+  float* v;              // [3][N]
+  float* out;            // [3][N]: Adam direction (mode 0) or gradient (mode 1)
+  double* partials;      // per-workgroup sum of cc
+  Ctl* ctl;
+  int n0, n1, n2;
+  int zc, tiles_y, tiles_x;
+  float eps_cc;
+  float beta1, beta2, adam_eps;
+  float inv_n;
+  int mode;
+};
+
+// ---- streaming separable Gaussian on a 3-channel field ---------------------
+enum GaussEpilogue { EPI_STORE = 0, EPI_MAXNORM = 1, EPI_COMPOSE = 2, EPI_STORE_FINAL = 3 };
+
+struct GaussArgs {
+  const float* in;       // [3][N]
+  float* out;            // [3][N] (store / compose)
+  const float* d;        // [3][N] displacement sampled by the composition
+  const float* wts;      // 2R+1 normalised taps (device)
+  Ctl* ctl;
+  const double* partials;  // loss partials of the gradient kernel (final epilogue)
+  float* loss_hist;
+  int loss_cap;
+  int n_partials;
+  float inv_n;
+  float eta;
+  int n0, n1, n2;
+  int zc, tiles_y, tiles_x;
+};
+
+// ---- launchers (fa_kernels.hip) -----------------------------------------
+hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s);
+hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s);
+hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s);
+hipError_t launch_blur_axis(const float* in, float* out, int n0, int n1, int n2, int axis,
+                            const float* wts, int radius, hipStream_t s);
+hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int nin2,
+                           int nout0, int nout1, int nout2, int nch,
+                           float rho0, float rho1, float rho2, hipStream_t s);
+hipError_t launch_warp(const float* img, const float* d, float* out, int n0, int n1, int n2,
+                       hipStream_t s);
+hipError_t launch_soa_to_aos(const float* in, float* out, int64_t n, hipStream_t s);
+// Sets the Adam step count to t_done + 1 (bias corrections in double), clears
+// M and the completion counter; iter >= 0 also resets the iteration counter.
+hipError_t launch_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int iter, hipStream_t s);
+// Mean of x (n values) into *dst (device float), via `scratch` (kMeanBlocks doubles).
+hipError_t launch_mean(const float* x, int64_t n, double* scratch, float* dst, hipStream_t s);
+hipError_t launch_sum_partials(const double* partials, int n, double* dst, hipStream_t s);
+constexpr int kMeanBlocks = 256;
+
+bool grad_tile_supported(int ty, int tx);
+bool gauss_tile_supported(int ty, int tx);
+size_t grad_lds_bytes(int window, int ty, int tx);
+size_t gauss_lds_bytes(int radius, int ty, int tx);
+
+constexpr int kMaxWindow = 9;
+constexpr int kMaxRadius = 6;
+
+}  // namespace fa

@@ -1,0 +1,807 @@
+// HIP kernels (gfx950) of the FireANTs dense matching step.
+//
+// One iteration of Algorithm 1 runs as four streaming launches:
+//
+//   grad   : warp J = I_m(x + d), LNCC window statistics, LNCC adjoint, the
+//            Gateaux gradient g = dL/dJ * grad_p I_m (Jacobian-free Eulerian
+//            descent, Section 4.4.2) and the Adam update (Section 4.4) ->
+//            m, v, direction a; per-workgroup loss partials.
+//   gauss  : s = G_sigma_grad * a, M = max |s|              (EPI_MAXNORM)
+//   gauss  : s again, u = -eta s / (2M) (Appendix E), d' = u + d(x + u)
+//            (the retraction phi o (id + u) of Algorithm 1)  (EPI_COMPOSE)
+//   gauss  : d = G_sigma_warp * d'; the last workgroup records the loss and
+//            advances the Adam step count                   (EPI_STORE_FINAL)
+//
+// Every streaming kernel gives a workgroup an in-plane tile (TY x TX columns
+// along n1, n2) and marches it along n0 over a chunk of planes.  Window sums
+// and Gaussian taps along n0 come from per-column register rings; the in-plane
+// parts are separable passes over halo tiles staged in LDS.  The path is a
+// stencil-and-gather workload bound by HBM bandwidth; there is no dense
+// contraction, so no MFMA.
+#include "fa_internal.h"
+
+namespace fa {
+namespace {
+
+__device__ __forceinline__ int vidx(int z, int y, int x, int n1, int n2) {
+  return (z * n1 + y) * n2 + x;
+}
+
+// Cell index and fraction of a sample coordinate, plus whether the lower and
+// upper corners lie on the grid.  Coordinates far outside are clamped first
+// (all corners are then off the grid anyway), which also keeps the integer
+// conversion defined.
+__device__ __forceinline__ void cell(float p, int n, int& i, float& t, bool& lo, bool& hi) {
+  p = fminf(fmaxf(p, -2.0f), (float)n + 1.0f);
+  const float f = floorf(p);
+  i = (int)f;
+  t = p - f;
+  lo = (i >= 0) & (i < n);
+  hi = (i >= -1) & (i + 1 < n);
+}
+
+// Load with per-corner zero padding; the address is always in bounds.
+__device__ __forceinline__ float ldz(const float* __restrict__ f, int idx, bool ok) {
+  const float v = f[ok ? idx : 0];
+  return ok ? v : 0.0f;
+}
+
+// The same for a sample at grid point x displaced by dd.  The cell index is
+// x + floor(dd) and the fraction dd - floor(dd), so no precision is lost to
+// forming x + dd in fp32: the cell is exactly the cell of the exact position
+// (the trilinear derivative jumps between cells, so the cell matters) and the
+// fraction is exact up to at most half an ulp of 1.
+__device__ __forceinline__ void cell_at(int x, float dd, int n, int& i, float& t, bool& lo, bool& hi) {
+  dd = fminf(fmaxf(dd, (float)(-x - 2)), (float)(n + 1 - x));
+  const float f = floorf(dd);
+  i = x + (int)f;
+  t = dd - f;
+  lo = (i >= 0) & (i < n);
+  hi = (i >= -1) & (i + 1 < n);
+}
+
+struct Corners {
+  int base, s0, s1;
+  bool a0, b0, a1, b1, a2, b2;
+  float t0, t1, t2;
+};
+
+// Corners of the sample at grid point (z, y, x) + (d0, d1, d2).
+__device__ __forceinline__ Corners corners_at(int n0, int n1, int n2, int z, int y, int x, float d0,
+                                              float d1, float d2) {
+  Corners c;
+  int i0, i1, i2;
+  cell_at(z, d0, n0, i0, c.t0, c.a0, c.b0);
+  cell_at(y, d1, n1, i1, c.t1, c.a1, c.b1);
+  cell_at(x, d2, n2, i2, c.t2, c.a2, c.b2);
+  c.s1 = n2;
+  c.s0 = n1 * n2;
+  c.base = (i0 * n1 + i1) * n2 + i2;
+  return c;
+}
+
+__device__ __forceinline__ Corners make_corners(int n0, int n1, int n2, float p0, float p1, float p2) {
+  Corners c;
+  int i0, i1, i2;
+  cell(p0, n0, i0, c.t0, c.a0, c.b0);
+  cell(p1, n1, i1, c.t1, c.a1, c.b1);
+  cell(p2, n2, i2, c.t2, c.a2, c.b2);
+  c.s1 = n2;
+  c.s0 = n1 * n2;
+  c.base = (i0 * n1 + i1) * n2 + i2;
+  return c;
+}
+
+// Trilinear sample T(f, p), zero outside the grid (per corner).
+__device__ __forceinline__ float tri(const float* __restrict__ f, const Corners& c) {
+  const float c000 = ldz(f, c.base, c.a0 & c.a1 & c.a2);
+  const float c001 = ldz(f, c.base + 1, c.a0 & c.a1 & c.b2);
+  const float c010 = ldz(f, c.base + c.s1, c.a0 & c.b1 & c.a2);
+  const float c011 = ldz(f, c.base + c.s1 + 1, c.a0 & c.b1 & c.b2);
+  const float c100 = ldz(f, c.base + c.s0, c.b0 & c.a1 & c.a2);
+  const float c101 = ldz(f, c.base + c.s0 + 1, c.b0 & c.a1 & c.b2);
+  const float c110 = ldz(f, c.base + c.s0 + c.s1, c.b0 & c.b1 & c.a2);
+  const float c111 = ldz(f, c.base + c.s0 + c.s1 + 1, c.b0 & c.b1 & c.b2);
+  const float e00 = c000 + c.t2 * (c001 - c000);
+  const float e01 = c010 + c.t2 * (c011 - c010);
+  const float e10 = c100 + c.t2 * (c101 - c100);
+  const float e11 = c110 + c.t2 * (c111 - c110);
+  const float f0 = e00 + c.t1 * (e01 - e00);
+  const float f1 = e10 + c.t1 * (e11 - e10);
+  return f0 + c.t0 * (f1 - f0);
+}
+
+// T(f, p) and dT/dp (the trilinear weight along one axis replaced by -1/+1;
+// at integer coordinates this is the derivative from the right).
+__device__ __forceinline__ float tri_grad(const float* __restrict__ f, const Corners& c,
+                                          float& g0, float& g1, float& g2) {
+  const float c000 = ldz(f, c.base, c.a0 & c.a1 & c.a2);
+  const float c001 = ldz(f, c.base + 1, c.a0 & c.a1 & c.b2);
+  const float c010 = ldz(f, c.base + c.s1, c.a0 & c.b1 & c.a2);
+  const float c011 = ldz(f, c.base + c.s1 + 1, c.a0 & c.b1 & c.b2);
+  const float c100 = ldz(f, c.base + c.s0, c.b0 & c.a1 & c.a2);
+  const float c101 = ldz(f, c.base + c.s0 + 1, c.b0 & c.a1 & c.b2);
+  const float c110 = ldz(f, c.base + c.s0 + c.s1, c.b0 & c.b1 & c.a2);
+  const float c111 = ldz(f, c.base + c.s0 + c.s1 + 1, c.b0 & c.b1 & c.b2);
+  const float dx00 = c001 - c000, dx01 = c011 - c010, dx10 = c101 - c100, dx11 = c111 - c110;
+  const float e00 = c000 + c.t2 * dx00;
+  const float e01 = c010 + c.t2 * dx01;
+  const float e10 = c100 + c.t2 * dx10;
+  const float e11 = c110 + c.t2 * dx11;
+  const float dy0 = e01 - e00, dy1 = e11 - e10;
+  const float f0 = e00 + c.t1 * dy0;
+  const float f1 = e10 + c.t1 * dy1;
+  const float dxy0 = dx00 + c.t1 * (dx01 - dx00);
+  const float dxy1 = dx10 + c.t1 * (dx11 - dx10);
+  g0 = f1 - f0;
+  g1 = dy0 + c.t0 * (dy1 - dy0);
+  g2 = dxy0 + c.t0 * (dxy1 - dxy0);
+  return f0 + c.t0 * (f1 - f0);
+}
+
+// Number of grid points of [i - r, i + r] inside [0, n).
+__device__ __forceinline__ float clipped_count(int i, int n, int r) {
+  return (float)(min(i + r, n - 1) - max(i - r, 0) + 1);
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+  }
+  return s;  // meaningful on thread 0
+}
+
+template <int NT>
+__device__ float block_max(float v, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  float s = 0.0f;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NT / 64; ++i) s = fmaxf(s, red[i]);
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Fused warp + LNCC + adjoint + Adam.
+//
+// Stage 1 (window statistics) runs on the tile plus a 2r halo: each column
+// keeps the last W planes of I and J in registers, sums them along n0, and
+// the in-plane box sums are two passes over LDS.  Stage 2 (adjoint box sums of
+// the per-centre coefficients A, B, C) runs on the tile plus an r halo:
+// in-plane passes first, then a register ring along n0.  The output plane
+// lags the input plane by 2r.
+// ---------------------------------------------------------------------------
+template <int W, int TY, int TX>
+__global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
+  constexpr int R = W / 2;
+  constexpr int NT = TY * TX;
+  constexpr int E1Y = TY + 4 * R, E1X = TX + 4 * R, E1 = E1Y * E1X;
+  constexpr int E2Y = TY + 2 * R, E2X = TX + 2 * R, E2 = E2Y * E2X;
+  constexpr int XS1 = E1Y * E2X;
+  constexpr int XS2 = E2Y * TX;
+  constexpr int CPT1 = (E1 + NT - 1) / NT;
+  extern __shared__ float lds[];
+  float* buf = lds;             // [5][E1], later [3][E2]
+  float* bufx = lds + 5 * E1;   // [5][XS1], later [3][XS2]
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  int b = blockIdx.x;
+  const int bx = b % A.tiles_x;
+  b /= A.tiles_x;
+  const int by = b % A.tiles_y;
+  b /= A.tiles_y;
+  const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
+  const int N = n0 * n1 * n2;
+  const int z0 = b * A.zc;
+  const int z1 = min(z0 + A.zc, n0);
+  const int y0 = by * TY, x0 = bx * TX;
+
+  int cy[CPT1], cx[CPT1];
+  bool cin[CPT1];
+#pragma unroll
+  for (int k = 0; k < CPT1; ++k) {
+    const int c = tid + k * NT;
+    cy[k] = y0 - 2 * R + c / E1X;
+    cx[k] = x0 - 2 * R + c % E1X;
+    cin[k] = (c < E1) && cy[k] >= 0 && cy[k] < n1 && cx[k] >= 0 && cx[k] < n2;
+  }
+  const int oy = tid / TX, ox = tid % TX;
+  const int gy = y0 + oy, gx = x0 + ox;
+  const bool out_col = gy < n1 && gx < n2;
+
+  float ringI[CPT1][W], ringJ[CPT1][W];
+  float ringA[W], ringB[W], ringC[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+#pragma unroll
+    for (int k = 0; k < CPT1; ++k) { ringI[k][j] = 0.0f; ringJ[k][j] = 0.0f; }
+    ringA[j] = ringB[j] = ringC[j] = 0.0f;
+  }
+
+  const float bc1 = A.ctl->bc1, bc2 = A.ctl->bc2;
+  if (A.mode == 0 && blockIdx.x == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
+  const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
+  double lacc = 0.0;
+
+  for (int zin = z0 - 2 * R; zin < z1 + 2 * R; ++zin) {
+    const bool zok = zin >= 0 && zin < n0;
+#pragma unroll
+    for (int k = 0; k < CPT1; ++k) {
+      float iv = 0.0f, jv = 0.0f;
+      if (zok && cin[k]) {
+        const int idx = vidx(zin, cy[k], cx[k], n1, n2);
+        iv = A.fixed[idx] - si;
+        const Corners c = corners_at(n0, n1, n2, zin, cy[k], cx[k], A.d[idx], A.d[N + idx], A.d[2 * N + idx]);
+        jv = tri(A.moving, c) - sj;
+      }
+#pragma unroll
+      for (int j = 0; j < W - 1; ++j) {
+        ringI[k][j] = ringI[k][j + 1];
+        ringJ[k][j] = ringJ[k][j + 1];
+      }
+      ringI[k][W - 1] = iv;
+      ringJ[k][W - 1] = jv;
+    }
+    if (zin < z0) continue;  // rings still filling; uniform across the workgroup
+
+#pragma unroll
+    for (int k = 0; k < CPT1; ++k) {
+      const int c = tid + k * NT;
+      if (c < E1) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const float i_ = ringI[k][j], j_ = ringJ[k][j];
+          s0 += i_;
+          s1 += j_;
+          s2 += i_ * i_;
+          s3 += j_ * j_;
+          s4 += i_ * j_;
+        }
+        buf[c] = s0;
+        buf[E1 + c] = s1;
+        buf[2 * E1 + c] = s2;
+        buf[3 * E1 + c] = s3;
+        buf[4 * E1 + c] = s4;
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < XS1; c += NT) {
+      const int yy = c / E2X, xo = c - yy * E2X;
+      const float* src = buf + yy * E1X + xo;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        s0 += src[k];
+        s1 += src[E1 + k];
+        s2 += src[2 * E1 + k];
+        s3 += src[3 * E1 + k];
+        s4 += src[4 * E1 + k];
+      }
+      bufx[c] = s0;
+      bufx[XS1 + c] = s1;
+      bufx[2 * XS1 + c] = s2;
+      bufx[3 * XS1 + c] = s3;
+      bufx[4 * XS1 + c] = s4;
+    }
+    __syncthreads();
+    const int zc1 = zin - R;
+    const bool z1ok = zc1 >= 0 && zc1 < n0;
+    const float cz = clipped_count(zc1, n0, R);
+    const bool z1out = zc1 >= z0 && zc1 < z1;
+    for (int c = tid; c < E2; c += NT) {
+      const int yo = c / E2X, xo = c - yo * E2X;
+      const float* src = bufx + yo * E2X + xo;
+      float SI = 0.f, SJ = 0.f, SII = 0.f, SJJ = 0.f, SIJ = 0.f;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        SI += src[k * E2X];
+        SJ += src[XS1 + k * E2X];
+        SII += src[2 * XS1 + k * E2X];
+        SJJ += src[3 * XS1 + k * E2X];
+        SIJ += src[4 * XS1 + k * E2X];
+      }
+      const int yy = y0 - R + yo, xx = x0 - R + xo;
+      float ca = 0.f, cb = 0.f, cc_ = 0.f;
+      // A one-voxel window has zero variance and zero covariance exactly, so
+      // its correlation and every coefficient are 0 (W == 1 skips the
+      // arithmetic that would leave rounding residue).
+      if (W > 1 && z1ok && yy >= 0 && yy < n1 && xx >= 0 && xx < n2) {
+        const float cnt = cz * clipped_count(yy, n1, R) * clipped_count(xx, n2, R);
+        const float muI = SI / cnt, muJ = SJ / cnt;
+        const float cross = SIJ - muI * SJ;
+        const float vI = SII - muI * SI;
+        const float vJ = SJJ - muJ * SJ;
+        const float D = vI * vJ + A.eps_cc;
+        if (D != 0.0f) {
+          const float invD = 1.0f / D;
+          const float cc = cross * cross * invD;
+          ca = 2.0f * cross * invD;
+          cb = -2.0f * cc * vI * invD;
+          cc_ = ca * muI + cb * muJ;
+          if (z1out && yo >= R && yo < R + TY && xo >= R && xo < R + TX) lacc += (double)cc;
+        }
+      }
+      buf[c] = ca;
+      buf[E2 + c] = cb;
+      buf[2 * E2 + c] = cc_;
+    }
+    __syncthreads();
+    for (int c = tid; c < XS2; c += NT) {
+      const int yy = c / TX, xo = c - yy * TX;
+      const float* src = buf + yy * E2X + xo;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        s0 += src[k];
+        s1 += src[E2 + k];
+        s2 += src[2 * E2 + k];
+      }
+      bufx[c] = s0;
+      bufx[XS2 + c] = s1;
+      bufx[2 * XS2 + c] = s2;
+    }
+    __syncthreads();
+    {
+      const float* src = bufx + oy * TX + ox;
+      float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        sa += src[k * TX];
+        sb += src[XS2 + k * TX];
+        sc += src[2 * XS2 + k * TX];
+      }
+#pragma unroll
+      for (int j = 0; j < W - 1; ++j) {
+        ringA[j] = ringA[j + 1];
+        ringB[j] = ringB[j + 1];
+        ringC[j] = ringC[j + 1];
+      }
+      ringA[W - 1] = sa;
+      ringB[W - 1] = sb;
+      ringC[W - 1] = sc;
+    }
+    const int zc2 = zc1 - R;
+    if (zc2 >= z0 && out_col) {
+      float SA = 0.f, SB = 0.f, SC = 0.f;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        SA += ringA[j];
+        SB += ringB[j];
+        SC += ringC[j];
+      }
+      const int idx = vidx(zc2, gy, gx, n1, n2);
+      const float iv = A.fixed[idx] - si;
+      const Corners c = corners_at(n0, n1, n2, zc2, gy, gx, A.d[idx], A.d[N + idx], A.d[2 * N + idx]);
+      float d0, d1, d2;
+      const float jv = tri_grad(A.moving, c, d0, d1, d2) - sj;
+      const float dl = -A.inv_n * (iv * SA + jv * SB - SC);
+      const float g[3] = {dl * d0, dl * d1, dl * d2};
+      if (A.mode == 0) {
+        const float b1 = A.beta1, b2 = A.beta2;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int iq = q * N + idx;
+          const float mm = b1 * A.m[iq] + (1.0f - b1) * g[q];
+          const float vv = b2 * A.v[iq] + (1.0f - b2) * g[q] * g[q];
+          A.m[iq] = mm;
+          A.v[iq] = vv;
+          A.out[iq] = (mm / bc1) / (sqrtf(vv / bc2) + A.adam_eps);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) A.out[q * N + idx] = g[q];
+      }
+    }
+  }
+  const double tot = block_sum<NT>(lacc, red);
+  if (tid == 0) A.partials[blockIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Separable Gaussian (replicate boundary) on a 3-channel field, streaming.
+// In-plane passes over a clamped halo tile in LDS, then a register ring of
+// 2R+1 planes per output column along n0.
+// ---------------------------------------------------------------------------
+template <int R, int TY, int TX, int EPI>
+__global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
+  constexpr int L = 2 * R + 1;
+  constexpr int NT = TY * TX;
+  constexpr int EY = TY + 2 * R, EX = TX + 2 * R, E = EY * EX;
+  constexpr int XS = EY * TX;
+  extern __shared__ float lds[];
+  float* buf = lds;           // [3][E]
+  float* bufx = lds + 3 * E;  // [3][XS]
+  __shared__ double red[NT / 64];
+  __shared__ int is_last;
+
+  const int tid = threadIdx.x;
+  int b = blockIdx.x;
+  const int bx = b % A.tiles_x;
+  b /= A.tiles_x;
+  const int by = b % A.tiles_y;
+  b /= A.tiles_y;
+  const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
+  const int N = n0 * n1 * n2;
+  const int z0 = b * A.zc;
+  const int z1 = min(z0 + A.zc, n0);
+  const int y0 = by * TY, x0 = bx * TX;
+  const int oy = tid / TX, ox = tid % TX;
+  const int gy = y0 + oy, gx = x0 + ox;
+  const bool out_col = gy < n1 && gx < n2;
+
+  float w[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) w[k] = A.wts[k];
+  float ring[3][L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) ring[0][k] = ring[1][k] = ring[2][k] = 0.0f;
+
+  float scale = 0.0f;
+  if (EPI == EPI_COMPOSE) {
+    const float M = __uint_as_float(A.ctl->mbits);
+    scale = M > 0.0f ? -A.eta / (2.0f * M) : 0.0f;
+  }
+  float mx = 0.0f;
+
+  for (int zin = z0 - R; zin < z1 + R; ++zin) {
+    const int zs = min(max(zin, 0), n0 - 1);
+    for (int c = tid; c < E; c += NT) {
+      const int yy = min(max(y0 - R + c / EX, 0), n1 - 1);
+      const int xx = min(max(x0 - R + c % EX, 0), n2 - 1);
+      const int idx = vidx(zs, yy, xx, n1, n2);
+      buf[c] = A.in[idx];
+      buf[E + c] = A.in[N + idx];
+      buf[2 * E + c] = A.in[2 * N + idx];
+    }
+    __syncthreads();
+    for (int c = tid; c < XS; c += NT) {
+      const int yy = c / TX, xo = c - yy * TX;
+      const float* src = buf + yy * EX + xo;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        s0 += w[k] * src[k];
+        s1 += w[k] * src[E + k];
+        s2 += w[k] * src[2 * E + k];
+      }
+      bufx[c] = s0;
+      bufx[XS + c] = s1;
+      bufx[2 * XS + c] = s2;
+    }
+    __syncthreads();
+    {
+      const float* src = bufx + oy * TX + ox;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        s0 += w[k] * src[k * TX];
+        s1 += w[k] * src[XS + k * TX];
+        s2 += w[k] * src[2 * XS + k * TX];
+      }
+#pragma unroll
+      for (int j = 0; j < L - 1; ++j) {
+        ring[0][j] = ring[0][j + 1];
+        ring[1][j] = ring[1][j + 1];
+        ring[2][j] = ring[2][j + 1];
+      }
+      ring[0][L - 1] = s0;
+      ring[1][L - 1] = s1;
+      ring[2][L - 1] = s2;
+    }
+    const int zo = zin - R;
+    if (zo >= z0 && out_col) {
+      float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        v0 += w[j] * ring[0][j];
+        v1 += w[j] * ring[1][j];
+        v2 += w[j] * ring[2][j];
+      }
+      const int idx = vidx(zo, gy, gx, n1, n2);
+      if (EPI == EPI_STORE || EPI == EPI_STORE_FINAL) {
+        A.out[idx] = v0;
+        A.out[N + idx] = v1;
+        A.out[2 * N + idx] = v2;
+      } else if (EPI == EPI_MAXNORM) {
+        mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
+      } else {  // EPI_COMPOSE
+        const float u0 = scale * v0, u1 = scale * v1, u2 = scale * v2;
+        const Corners c = corners_at(n0, n1, n2, zo, gy, gx, u0, u1, u2);
+        A.out[idx] = u0 + tri(A.d, c);
+        A.out[N + idx] = u1 + tri(A.d + N, c);
+        A.out[2 * N + idx] = u2 + tri(A.d + 2 * N, c);
+      }
+    }
+  }
+
+  if (EPI == EPI_MAXNORM) {
+    const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
+    if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
+  }
+  if (EPI == EPI_STORE_FINAL) {
+    // The last workgroup to finish records the iteration's loss and advances
+    // the Adam step count; every workgroup of this launch has read nothing
+    // from the control block, so the update cannot race.
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const unsigned prev = atomicAdd(&A.ctl->ticket, 1u);
+      is_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (is_last) {
+      __threadfence();
+      double s = 0.0;
+      for (int i = tid; i < A.n_partials; i += NT) s += A.partials[i];
+      s = block_sum<NT>(s, red);
+      if (tid == 0) {
+        const int t = A.ctl->t;
+        const int it = A.ctl->iter;
+        if (A.loss_hist && it >= 0 && it < A.loss_cap) A.loss_hist[it] = (float)(-s * (double)A.inv_n);
+        A.ctl->iter = it + 1;
+        A.ctl->t = t + 1;
+        A.ctl->bc1 = (float)(1.0 - pow((double)A.ctl->beta1, (double)(t + 1)));
+        A.ctl->bc2 = (float)(1.0 - pow((double)A.ctl->beta2, (double)(t + 1)));
+        A.ctl->ticket = 0u;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Off-loop kernels: pyramid blur and resampling, warp, fills, layout copies.
+// ---------------------------------------------------------------------------
+__global__ void k_fill(float* __restrict__ p, float value, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+__global__ void k_blur_axis(const float* __restrict__ in, float* __restrict__ out, int n0, int n1,
+                            int n2, int axis, const float* __restrict__ w, int R) {
+  const int N = n0 * n1 * n2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int x = i % n2, y = (i / n2) % n1, z = i / (n1 * n2);
+  const int pos = axis == 0 ? z : (axis == 1 ? y : x);
+  const int n = axis == 0 ? n0 : (axis == 1 ? n1 : n2);
+  const int stride = axis == 0 ? n1 * n2 : (axis == 1 ? n2 : 1);
+  float s = 0.0f;
+  for (int k = -R; k <= R; ++k) {
+    const int q = min(max(pos + k, 0), n - 1);
+    s += w[k + R] * in[i + (q - pos) * stride];
+  }
+  out[i] = s;
+}
+
+__device__ __forceinline__ float aligned_pos(int i, int nin, int nout) {
+  return nout > 1 ? (float)(i * (nin - 1)) / (float)(nout - 1) : 0.0f;
+}
+
+__global__ void k_resample(const float* __restrict__ in, float* __restrict__ out, int ni0, int ni1,
+                           int ni2, int no0, int no1, int no2, int nch, float rho0, float rho1,
+                           float rho2) {
+  const int No = no0 * no1 * no2;
+  const int Ni = ni0 * ni1 * ni2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= No) return;
+  const int x = i % no2, y = (i / no2) % no1, z = i / (no1 * no2);
+  const Corners c = make_corners(ni0, ni1, ni2, aligned_pos(z, ni0, no0), aligned_pos(y, ni1, no1),
+                                 aligned_pos(x, ni2, no2));
+  out[i] = rho0 * tri(in, c);
+  if (nch > 1) {
+    out[No + i] = rho1 * tri(in + Ni, c);
+    out[2 * No + i] = rho2 * tri(in + 2 * Ni, c);
+  }
+}
+
+__global__ void k_warp(const float* __restrict__ img, const float* __restrict__ d,
+                       float* __restrict__ out, int n0, int n1, int n2) {
+  const int N = n0 * n1 * n2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int x = i % n2, y = (i / n2) % n1, z = i / (n1 * n2);
+  const Corners c = corners_at(n0, n1, n2, z, y, x, d[i], d[N + i], d[2 * N + i]);
+  out[i] = tri(img, c);
+}
+
+__global__ void k_soa_to_aos(const float* __restrict__ in, float* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[3 * i] = in[i];
+  out[3 * i + 1] = in[n + i];
+  out[3 * i + 2] = in[2 * n + i];
+}
+
+__global__ void k_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int iter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int t = t_done + 1;
+    ctl->t = t;
+    if (iter >= 0) ctl->iter = iter;
+    ctl->beta1 = beta1;
+    ctl->beta2 = beta2;
+    ctl->bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+    ctl->bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    ctl->mbits = 0u;
+    ctl->ticket = 0u;
+  }
+}
+
+__global__ void k_sum_partial(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[i];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_mean_final(const double* __restrict__ part, int np, double n, float* __restrict__ dst) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) *dst = (float)(s / n);
+}
+
+__global__ void k_sum_final(const double* __restrict__ part, int np, double* __restrict__ dst) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) *dst = s;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch tables
+// ---------------------------------------------------------------------------
+template <int W, int TY, int TX>
+constexpr size_t grad_lds() {
+  constexpr int R = W / 2;
+  return sizeof(float) * (5 * (TY + 4 * R) * (TX + 4 * R) + 5 * (TY + 4 * R) * (TX + 2 * R));
+}
+
+template <int R, int TY, int TX>
+constexpr size_t gauss_lds() {
+  return sizeof(float) * (3 * (TY + 2 * R) * (TX + 2 * R) + 3 * (TY + 2 * R) * TX);
+}
+
+template <int W, int TY, int TX>
+hipError_t grad_launch_t(const GradArgs& a, const Tiling& t, hipStream_t s) {
+  constexpr size_t sh = grad_lds<W, TY, TX>();
+  k_grad<W, TY, TX><<<dim3(t.blocks()), dim3(TY * TX), sh, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int TY, int TX>
+hipError_t grad_launch_tile(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
+  switch (window) {
+    case 1: return grad_launch_t<1, TY, TX>(a, t, s);
+    case 3: return grad_launch_t<3, TY, TX>(a, t, s);
+    case 5: return grad_launch_t<5, TY, TX>(a, t, s);
+    case 7: return grad_launch_t<7, TY, TX>(a, t, s);
+    case 9: return grad_launch_t<9, TY, TX>(a, t, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int R, int TY, int TX>
+hipError_t gauss_launch_r(const GaussArgs& a, int epi, const Tiling& t, hipStream_t s) {
+  const dim3 g(t.blocks()), blk(TY * TX);
+  const size_t sh = gauss_lds<R, TY, TX>();
+  switch (epi) {
+    case EPI_STORE: k_gauss<R, TY, TX, EPI_STORE><<<g, blk, sh, s>>>(a); break;
+    case EPI_MAXNORM: k_gauss<R, TY, TX, EPI_MAXNORM><<<g, blk, sh, s>>>(a); break;
+    case EPI_COMPOSE: k_gauss<R, TY, TX, EPI_COMPOSE><<<g, blk, sh, s>>>(a); break;
+    case EPI_STORE_FINAL: k_gauss<R, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int TY, int TX>
+hipError_t gauss_launch_tile(const GaussArgs& a, int radius, int epi, const Tiling& t, hipStream_t s) {
+  switch (radius) {
+    case 0: return gauss_launch_r<0, TY, TX>(a, epi, t, s);
+    case 1: return gauss_launch_r<1, TY, TX>(a, epi, t, s);
+    case 2: return gauss_launch_r<2, TY, TX>(a, epi, t, s);
+    case 3: return gauss_launch_r<3, TY, TX>(a, epi, t, s);
+    case 4: return gauss_launch_r<4, TY, TX>(a, epi, t, s);
+    case 5: return gauss_launch_r<5, TY, TX>(a, epi, t, s);
+    case 6: return gauss_launch_r<6, TY, TX>(a, epi, t, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool grad_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
+bool gauss_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
+
+size_t grad_lds_bytes(int window, int ty, int tx) {
+  const int R = window / 2;
+  return sizeof(float) * (size_t)(5 * (ty + 4 * R) * (tx + 4 * R) + 5 * (ty + 4 * R) * (tx + 2 * R));
+}
+
+size_t gauss_lds_bytes(int radius, int ty, int tx) {
+  return sizeof(float) * (size_t)(3 * (ty + 2 * radius) * (tx + 2 * radius) + 3 * (ty + 2 * radius) * tx);
+}
+
+hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
+  if (t.ty == 16 && t.tx == 32) return grad_launch_tile<16, 32>(a, window, t, s);
+  if (t.ty == 8 && t.tx == 32) return grad_launch_tile<8, 32>(a, window, t, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
+  if (t.ty == 16 && t.tx == 32) return gauss_launch_tile<16, 32>(a, radius, epilogue, t, s);
+  if (t.ty == 8 && t.tx == 32) return gauss_launch_tile<8, 32>(a, radius, epilogue, t, s);
+  return hipErrorInvalidValue;
+}
+
+static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid1(n, 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_blur_axis(const float* in, float* out, int n0, int n1, int n2, int axis,
+                            const float* wts, int radius, hipStream_t s) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  hipLaunchKernelGGL(k_blur_axis, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, n0, n1, n2, axis, wts, radius);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int nin2, int nout0,
+                           int nout1, int nout2, int nch, float rho0, float rho1, float rho2,
+                           hipStream_t s) {
+  const int64_t n = (int64_t)nout0 * nout1 * nout2;
+  hipLaunchKernelGGL(k_resample, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, nin0, nin1, nin2, nout0,
+                     nout1, nout2, nch, rho0, rho1, rho2);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp(const float* img, const float* d, float* out, int n0, int n1, int n2, hipStream_t s) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  hipLaunchKernelGGL(k_warp, dim3(grid1(n, 256)), dim3(256), 0, s, img, d, out, n0, n1, n2);
+  return hipGetLastError();
+}
+
+hipError_t launch_soa_to_aos(const float* in, float* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_soa_to_aos, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, beta1, beta2, t_done, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean(const float* x, int64_t n, double* scratch, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partial, dim3(kMeanBlocks), dim3(256), 0, s, x, n, scratch);
+  hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(256), 0, s, scratch, kMeanBlocks, (double)n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partials, int n, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partials, n, dst);
+  return hipGetLastError();
+}
+
+}  // namespace fa

@@ -1,0 +1,723 @@
+// Host runtime of the C ABI (include/fa.h, include/fa_inspect.h): the pair
+// object, its device buffers, the pyramid, the level/iteration driver of
+// Algorithm 1 and the error reporting.  All device work is enqueued on the
+// pair's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fa.h"
+#include "fa_inspect.h"
+#include "fa_internal.h"
+
+using fa::Ctl;
+using fa::Tiling;
+
+namespace {
+
+thread_local std::string g_err;
+
+fa_status fail(fa_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define FA_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(FA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+#define FA_TRY(call)                       \
+  do {                                     \
+    fa_status s_ = (call);                 \
+    if (s_ != FA_OK) return s_;            \
+  } while (0)
+
+int64_t voxels(const fa_shape& s) { return (int64_t)s.n0 * s.n1 * s.n2; }
+
+// Sampled Gaussian taps exp(-k^2 / 2 sigma^2), |k| <= ceil(3 sigma),
+// normalised to sum 1 (computed in double).  sigma <= 0 gives the single tap 1.
+std::vector<float> gaussian_taps(float sigma_f) {
+  const double s = (double)sigma_f;
+  if (!(s > 0.0)) return {1.0f};
+  const int R = (int)std::ceil(3.0 * s);
+  std::vector<double> w(2 * R + 1);
+  double tot = 0.0;
+  for (int k = -R; k <= R; ++k) {
+    w[k + R] = std::exp(-(double)k * k / (2.0 * s * s));
+    tot += w[k + R];
+  }
+  std::vector<float> out(w.size());
+  for (size_t i = 0; i < w.size(); ++i) out[i] = (float)(w[i] / tot);
+  return out;
+}
+
+int tap_radius(float sigma) { return (int)(gaussian_taps(sigma).size() / 2); }
+
+// In-plane tile and n0 chunking of one streaming launch.  halo = planes of
+// look-ahead the kernel needs on each side of its chunk.
+Tiling choose_tiling(const fa_shape& s, int halo) {
+  Tiling t;
+  t.tx = 32;
+  t.ty = (s.n1 * s.n2 >= 128 * 128) ? 16 : 8;
+  t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
+  t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
+  const int plane_tiles = t.tiles_y * t.tiles_x;
+  const int target = (t.ty == 16) ? 640 : 1024;       // workgroups in flight
+  int chunks = std::max(1, (target + plane_tiles - 1) / plane_tiles);
+  int zc = (s.n0 + chunks - 1) / chunks;
+  zc = std::max(zc, std::max(4, halo));
+  zc = std::min(zc, s.n0);
+  t.zc = zc;
+  t.chunks = (s.n0 + zc - 1) / zc;
+  return t;
+}
+
+struct Level {
+  fa_shape shape{};
+  int64_t n = 0;
+  float scale = 1.0f;
+  int iters = 0;
+  float* fixed = nullptr;   // owned unless it aliases the input copy
+  float* moving = nullptr;
+  bool owns = false;
+  Tiling tg{}, tsg{}, tsw{};  // gradient, sigma_grad and sigma_warp launches
+};
+
+}  // namespace
+
+struct fa_pair_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  fa_shape shape{};
+  int64_t n = 0;
+  fa_params p{};
+  float* in_fixed = nullptr;
+  float* in_moving = nullptr;
+  std::vector<Level> levels;
+  int64_t cap = 0;            // voxels each state buffer can hold
+  float* d = nullptr;         // state at the current level, SoA [3][n]
+  float* m = nullptr;
+  float* v = nullptr;
+  float* a = nullptr;         // Adam direction
+  float* tmp = nullptr;       // composed displacement before sigma_warp
+  float* blur0 = nullptr;     // pyramid scratch (input size)
+  float* blur1 = nullptr;
+  Ctl* ctl = nullptr;
+  float* loss_hist = nullptr;
+  int loss_cap = 0;
+  double* partials = nullptr;
+  int partials_cap = 0;
+  double* scratch = nullptr;  // kMeanBlocks + 1 doubles
+  float* wts = nullptr;       // device tap tables
+  std::vector<float> wts_host;
+  int rg = 0, rw = 0;         // Gaussian radii (sigma_grad, sigma_warp)
+  int off_g = 0, off_w = 0;   // offsets of their taps in wts
+  std::vector<int> off_blur;  // per level, pyramid blur taps
+  // kernel timing (fa_pair_profile)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending { hipEvent_t e[5]; int level; };
+  std::vector<Pending> pending;
+  std::vector<double> prof_ms;   // [level][kind]
+  std::vector<int> prof_n;
+  int cur_level = 0, cur_iter = 0;
+  int t_done = 0;      // Adam steps taken (set_state may change it)
+  int iters_done = 0;  // schedule iterations run = losses recorded
+  bool scheduled = false;
+};
+
+namespace {
+
+void free_levels(fa_pair P) {
+  for (auto& L : P->levels) {
+    if (L.owns) {
+      (void)hipFree(L.fixed);
+      (void)hipFree(L.moving);
+    }
+  }
+  P->levels.clear();
+}
+
+void free_all(fa_pair P) {
+  free_levels(P);
+  float* fbufs[] = {P->in_fixed, P->in_moving, P->d, P->m, P->v, P->a, P->tmp, P->blur0,
+                    P->blur1, P->loss_hist, P->wts};
+  for (float* b : fbufs)
+    if (b) (void)hipFree(b);
+  if (P->ctl) (void)hipFree(P->ctl);
+  if (P->partials) (void)hipFree(P->partials);
+  if (P->scratch) (void)hipFree(P->scratch);
+}
+
+template <typename T>
+fa_status dalloc(T** out, size_t count, const char* what) {
+  *out = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)out, count * sizeof(T));
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(FA_ENOMEM, std::string("hipMalloc failed for ") + what + " (" +
+                               std::to_string(count * sizeof(T)) + " bytes): " + hipGetErrorString(e));
+  }
+  return FA_OK;
+}
+
+fa_status check_params(const fa_params* p) {
+  if (!p) return fail(FA_EINVAL, "params is NULL");
+  if (!(p->eta > 0.0f) || !std::isfinite(p->eta)) return fail(FA_EINVAL, "eta must be a finite value > 0");
+  if (p->cc_window < 1 || p->cc_window > fa::kMaxWindow || (p->cc_window % 2) == 0)
+    return fail(FA_EINVAL, "cc_window must be odd and in [1, 9]");
+  if (!(p->cc_eps >= 0.0f) || !std::isfinite(p->cc_eps)) return fail(FA_EINVAL, "cc_eps must be finite and >= 0");
+  if (!(p->adam_beta1 >= 0.0f && p->adam_beta1 < 1.0f)) return fail(FA_EINVAL, "adam_beta1 must be in [0, 1)");
+  if (!(p->adam_beta2 >= 0.0f && p->adam_beta2 < 1.0f)) return fail(FA_EINVAL, "adam_beta2 must be in [0, 1)");
+  if (!(p->adam_eps >= 0.0f) || !std::isfinite(p->adam_eps)) return fail(FA_EINVAL, "adam_eps must be finite and >= 0");
+  if (!std::isfinite(p->sigma_grad) || !std::isfinite(p->sigma_warp))
+    return fail(FA_EINVAL, "sigma_grad and sigma_warp must be finite");
+  if (tap_radius(p->sigma_grad) > fa::kMaxRadius || tap_radius(p->sigma_warp) > fa::kMaxRadius)
+    return fail(FA_EINVAL, "Gaussian radius ceil(3 sigma) must be <= 6 (sigma <= 2 voxels)");
+  if (p->use_jac != 0) return fail(FA_EINVAL, "use_jac = 1 (Jacobian-augmented descent) is not supported");
+  return FA_OK;
+}
+
+fa_status check_shape(const fa_shape& s) {
+  if (s.n0 < 2 || s.n1 < 2 || s.n2 < 2) return fail(FA_ESHAPE, "every dimension must be >= 2");
+  if (3 * (double)s.n0 * s.n1 * s.n2 >= 2147483647.0)
+    return fail(FA_ESHAPE, "volume too large: 3*n0*n1*n2 must be < 2^31");
+  return FA_OK;
+}
+
+fa_shape level_shape(const fa_shape& s, float scale) {
+  const double sc = (double)scale;
+  auto one = [&](int n) { return std::max(1, (int)std::floor((double)n / sc + 0.5)); };
+  return fa_shape{one(s.n0), one(s.n1), one(s.n2)};
+}
+
+// Blur (sigma = scale/2, replicate) then resample at corner-aligned positions.
+fa_status build_level_image(fa_pair P, const float* src, float* dst, const Level& L, int off) {
+  const fa_shape& s = P->shape;
+  const int rad = tap_radius(L.scale / 2.0f);
+  const float* w = P->wts + off;
+  FA_HIP(fa::launch_blur_axis(src, P->blur0, s.n0, s.n1, s.n2, 0, w, rad, P->stream));
+  FA_HIP(fa::launch_blur_axis(P->blur0, P->blur1, s.n0, s.n1, s.n2, 1, w, rad, P->stream));
+  FA_HIP(fa::launch_blur_axis(P->blur1, P->blur0, s.n0, s.n1, s.n2, 2, w, rad, P->stream));
+  FA_HIP(fa::launch_resample(P->blur0, dst, s.n0, s.n1, s.n2, L.shape.n0, L.shape.n1, L.shape.n2, 1,
+                             1.0f, 1.0f, 1.0f, P->stream));
+  return FA_OK;
+}
+
+fa_status get_event(fa_pair P, hipEvent_t* e) {
+  if (!P->ev_pool.empty()) {
+    *e = P->ev_pool.back();
+    P->ev_pool.pop_back();
+    return FA_OK;
+  }
+  FA_HIP(hipEventCreate(e));
+  return FA_OK;
+}
+
+// Fold recorded event pairs into the per-level totals (synchronises).
+fa_status drain_profile(fa_pair P) {
+  if (P->pending.empty()) return FA_OK;
+  FA_HIP(hipStreamSynchronize(P->stream));
+  for (auto& pe : P->pending) {
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.0f;
+      FA_HIP(hipEventElapsedTime(&ms, pe.e[k], pe.e[k + 1]));
+      const size_t slot = (size_t)pe.level * 4 + k;
+      if (slot < P->prof_ms.size()) {
+        P->prof_ms[slot] += ms;
+        P->prof_n[slot] += 1;
+      }
+    }
+    for (int k = 0; k < 5; ++k) P->ev_pool.push_back(pe.e[k]);
+  }
+  P->pending.clear();
+  return FA_OK;
+}
+
+fa_status launch_iteration(fa_pair P, const Level& L) {
+  const int w = P->p.cc_window;
+  fa_pair_s::Pending pe{};
+  pe.level = P->cur_level;
+  if (P->profiling) {
+    for (int k = 0; k < 5; ++k) FA_TRY(get_event(P, &pe.e[k]));
+    FA_HIP(hipEventRecord(pe.e[0], P->stream));
+  }
+  fa::GradArgs ga{};
+  ga.fixed = L.fixed;
+  ga.moving = L.moving;
+  ga.d = P->d;
+  ga.m = P->m;
+  ga.v = P->v;
+  ga.out = P->a;
+  ga.partials = P->partials;
+  ga.ctl = P->ctl;
+  ga.n0 = L.shape.n0;
+  ga.n1 = L.shape.n1;
+  ga.n2 = L.shape.n2;
+  ga.zc = L.tg.zc;
+  ga.tiles_y = L.tg.tiles_y;
+  ga.tiles_x = L.tg.tiles_x;
+  ga.eps_cc = P->p.cc_eps;
+  ga.beta1 = P->p.adam_beta1;
+  ga.beta2 = P->p.adam_beta2;
+  ga.adam_eps = P->p.adam_eps;
+  ga.inv_n = (float)(1.0 / (double)L.n);
+  ga.mode = 0;
+  FA_HIP(fa::launch_grad(ga, w, L.tg, P->stream));
+  if (P->profiling) FA_HIP(hipEventRecord(pe.e[1], P->stream));
+
+  fa::GaussArgs gs{};
+  gs.ctl = P->ctl;
+  gs.n0 = L.shape.n0;
+  gs.n1 = L.shape.n1;
+  gs.n2 = L.shape.n2;
+  gs.eta = P->p.eta;
+  gs.inv_n = (float)(1.0 / (double)L.n);
+
+  fa::GaussArgs g1 = gs;  // M = max |G * a|
+  g1.in = P->a;
+  g1.wts = P->wts + P->off_g;
+  g1.zc = L.tsg.zc;
+  g1.tiles_y = L.tsg.tiles_y;
+  g1.tiles_x = L.tsg.tiles_x;
+  FA_HIP(fa::launch_gauss(g1, P->rg, fa::EPI_MAXNORM, L.tsg, P->stream));
+  if (P->profiling) FA_HIP(hipEventRecord(pe.e[2], P->stream));
+
+  fa::GaussArgs g2 = g1;  // d' = u + d(x + u)
+  g2.out = P->tmp;
+  g2.d = P->d;
+  FA_HIP(fa::launch_gauss(g2, P->rg, fa::EPI_COMPOSE, L.tsg, P->stream));
+  if (P->profiling) FA_HIP(hipEventRecord(pe.e[3], P->stream));
+
+  fa::GaussArgs g3 = gs;  // d = G * d'; record loss, advance t
+  g3.in = P->tmp;
+  g3.out = P->d;
+  g3.wts = P->wts + P->off_w;
+  g3.zc = L.tsw.zc;
+  g3.tiles_y = L.tsw.tiles_y;
+  g3.tiles_x = L.tsw.tiles_x;
+  g3.partials = P->partials;
+  g3.n_partials = L.tg.blocks();
+  g3.loss_hist = P->loss_hist;
+  g3.loss_cap = P->loss_cap;
+  FA_HIP(fa::launch_gauss(g3, P->rw, fa::EPI_STORE_FINAL, L.tsw, P->stream));
+  if (P->profiling) {
+    FA_HIP(hipEventRecord(pe.e[4], P->stream));
+    P->pending.push_back(pe);
+    if (P->pending.size() >= 4096) FA_TRY(drain_profile(P));
+  }
+  return FA_OK;
+}
+
+// Carry d (rescaled to the new voxel units), m and v to the next level.
+fa_status transition(fa_pair P) {
+  const Level& C = P->levels[P->cur_level];
+  const Level& F = P->levels[P->cur_level + 1];
+  auto rho = [](int nf, int nc) { return nc > 1 ? (float)((double)(nf - 1) / (double)(nc - 1)) : 1.0f; };
+  const float r0 = rho(F.shape.n0, C.shape.n0), r1 = rho(F.shape.n1, C.shape.n1), r2 = rho(F.shape.n2, C.shape.n2);
+  const fa_shape& c = C.shape;
+  const fa_shape& f = F.shape;
+  FA_HIP(fa::launch_resample(P->d, P->tmp, c.n0, c.n1, c.n2, f.n0, f.n1, f.n2, 3, r0, r1, r2, P->stream));
+  FA_HIP(fa::launch_resample(P->m, P->a, c.n0, c.n1, c.n2, f.n0, f.n1, f.n2, 3, 1.f, 1.f, 1.f, P->stream));
+  // v's coarse data moves into the buffer that held m (already consumed).
+  FA_HIP(fa::launch_resample(P->v, P->m, c.n0, c.n1, c.n2, f.n0, f.n1, f.n2, 3, 1.f, 1.f, 1.f, P->stream));
+  float* old_d = P->d;
+  float* old_m = P->m;
+  float* old_v = P->v;
+  float* old_a = P->a;
+  float* old_t = P->tmp;
+  P->d = old_t;
+  P->m = old_a;
+  P->v = old_m;
+  P->a = old_d;
+  P->tmp = old_v;
+  return FA_OK;
+}
+
+// Advance past finished levels (upsampling at each boundary) while another
+// level remains.
+fa_status advance_levels(fa_pair P) {
+  while (P->cur_level + 1 < (int)P->levels.size() && P->cur_iter >= P->levels[P->cur_level].iters) {
+    FA_TRY(transition(P));
+    P->cur_level += 1;
+    P->cur_iter = 0;
+  }
+  return FA_OK;
+}
+
+bool schedule_done(const fa_pair P) {
+  return P->cur_level == (int)P->levels.size() - 1 && P->cur_iter >= P->levels.back().iters;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fa_last_error(void) { return g_err.c_str(); }
+
+fa_status fa_params_default(fa_params* out) {
+  if (!out) return fail(FA_EINVAL, "out is NULL");
+  out->eta = 0.5f;
+  out->sigma_grad = 1.0f;
+  out->sigma_warp = 0.5f;
+  out->cc_window = 5;
+  out->cc_eps = 1e-5f;
+  out->adam_beta1 = 0.9f;
+  out->adam_beta2 = 0.999f;
+  out->adam_eps = 1e-8f;
+  out->use_jac = 0;
+  return FA_OK;
+}
+
+fa_status fa_pair_create(const float* fixed_dev, const float* moving_dev, fa_shape shape,
+                         const fa_params* p, void* hip_stream, fa_pair* out) {
+  if (!out) return fail(FA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!fixed_dev || !moving_dev) return fail(FA_EINVAL, "fixed and moving must be device pointers");
+  FA_TRY(check_shape(shape));
+  FA_TRY(check_params(p));
+  fa_pair P = new (std::nothrow) fa_pair_s();
+  if (!P) return fail(FA_ENOMEM, "host allocation failed");
+  P->stream = (hipStream_t)hip_stream;
+  P->shape = shape;
+  P->n = voxels(shape);
+  P->p = *p;
+  (void)hipGetDevice(&P->device);
+  fa_status st = FA_OK;
+  const size_t bytes = (size_t)P->n * sizeof(float);
+  if ((st = dalloc(&P->in_fixed, P->n, "fixed")) != FA_OK ||
+      (st = dalloc(&P->in_moving, P->n, "moving")) != FA_OK ||
+      (st = dalloc(&P->ctl, 1, "control block")) != FA_OK ||
+      (st = dalloc(&P->scratch, fa::kMeanBlocks + 1, "scratch")) != FA_OK) {
+    free_all(P);
+    delete P;
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(P->in_fixed, fixed_dev, bytes, hipMemcpyDeviceToDevice, P->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->in_moving, moving_dev, bytes, hipMemcpyDeviceToDevice, P->stream);
+  if (e != hipSuccess) {
+    free_all(P);
+    delete P;
+    return fail(FA_EHIP, std::string("copying the input volumes: ") + hipGetErrorString(e));
+  }
+  *out = P;
+  return FA_OK;
+}
+
+fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, const int* iters) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (n_levels < 1 || n_levels > 16) return fail(FA_EINVAL, "n_levels must be in [1, 16]");
+  if (!scales || !iters) return fail(FA_EINVAL, "scales and iters must not be NULL");
+  std::vector<Level> lv(n_levels);
+  int64_t total_iters = 0, nmax = 0;
+  int pmax = 1;
+  const int r = P->p.cc_window / 2;
+  P->rg = tap_radius(P->p.sigma_grad);
+  P->rw = tap_radius(P->p.sigma_warp);
+  for (int i = 0; i < n_levels; ++i) {
+    if (!(scales[i] >= 1.0f) || !(scales[i] <= 20.0f))
+      return fail(FA_EINVAL, "scales must be in [1, 20]");
+    if (iters[i] < 0) return fail(FA_EINVAL, "iters must be >= 0");
+    lv[i].scale = scales[i];
+    lv[i].iters = iters[i];
+    lv[i].shape = level_shape(P->shape, scales[i]);
+    lv[i].n = voxels(lv[i].shape);
+    if (lv[i].shape.n0 < 2 || lv[i].shape.n1 < 2 || lv[i].shape.n2 < 2)
+      return fail(FA_ESHAPE, "level " + std::to_string(i) + " has a dimension < 2");
+    lv[i].tg = choose_tiling(lv[i].shape, 2 * r);
+    lv[i].tsg = choose_tiling(lv[i].shape, P->rg);
+    lv[i].tsw = choose_tiling(lv[i].shape, P->rw);
+    total_iters += iters[i];
+    nmax = std::max(nmax, lv[i].n);
+    pmax = std::max(pmax, lv[i].tg.blocks());
+  }
+  if (total_iters > (int64_t)1 << 30) return fail(FA_EINVAL, "too many iterations");
+
+  // Release a previous schedule's pyramid and history.
+  (void)hipStreamSynchronize(P->stream);
+  free_levels(P);
+  P->scheduled = false;
+
+  // Tap tables: sigma_grad, sigma_warp, then one per level for the blur.
+  P->wts_host.clear();
+  auto push = [&](const std::vector<float>& t) {
+    const int off = (int)P->wts_host.size();
+    P->wts_host.insert(P->wts_host.end(), t.begin(), t.end());
+    while (P->wts_host.size() % 16) P->wts_host.push_back(0.0f);
+    return off;
+  };
+  P->off_g = push(gaussian_taps(P->p.sigma_grad));
+  P->off_w = push(gaussian_taps(P->p.sigma_warp));
+  P->off_blur.assign(n_levels, 0);
+  for (int i = 0; i < n_levels; ++i) P->off_blur[i] = push(gaussian_taps(lv[i].scale / 2.0f));
+  if (P->wts) (void)hipFree(P->wts);
+  P->wts = nullptr;
+  FA_TRY(dalloc(&P->wts, P->wts_host.size(), "tap tables"));
+  FA_HIP(hipMemcpyAsync(P->wts, P->wts_host.data(), P->wts_host.size() * sizeof(float),
+                        hipMemcpyHostToDevice, P->stream));
+
+  if (nmax > P->cap) {
+    float** bufs[] = {&P->d, &P->m, &P->v, &P->a, &P->tmp};
+    for (float** b : bufs) {
+      if (*b) (void)hipFree(*b);
+      *b = nullptr;
+    }
+    P->cap = 0;
+    for (float** b : bufs) FA_TRY(dalloc(b, (size_t)3 * nmax, "state"));
+    P->cap = nmax;
+  }
+  if (total_iters > P->loss_cap) {
+    if (P->loss_hist) (void)hipFree(P->loss_hist);
+    P->loss_hist = nullptr;
+    P->loss_cap = 0;
+    FA_TRY(dalloc(&P->loss_hist, (size_t)total_iters, "loss history"));
+    P->loss_cap = (int)total_iters;
+  }
+  if (pmax > P->partials_cap) {
+    if (P->partials) (void)hipFree(P->partials);
+    P->partials = nullptr;
+    P->partials_cap = 0;
+    FA_TRY(dalloc(&P->partials, (size_t)pmax, "loss partials"));
+    P->partials_cap = pmax;
+  }
+
+  // Pyramid.
+  bool need_blur = false;
+  for (auto& L : lv) need_blur |= !(L.scale == 1.0f);
+  if (need_blur && !P->blur0) {
+    FA_TRY(dalloc(&P->blur0, (size_t)P->n, "pyramid scratch"));
+    FA_TRY(dalloc(&P->blur1, (size_t)P->n, "pyramid scratch"));
+  }
+  P->levels = lv;
+  for (int i = 0; i < n_levels; ++i) {
+    Level& L = P->levels[i];
+    if (L.scale == 1.0f) {
+      L.fixed = P->in_fixed;
+      L.moving = P->in_moving;
+      L.owns = false;
+      continue;
+    }
+    fa_status st;
+    if ((st = dalloc(&L.fixed, (size_t)L.n, "pyramid")) != FA_OK) return st;
+    if ((st = dalloc(&L.moving, (size_t)L.n, "pyramid")) != FA_OK) {
+      (void)hipFree(L.fixed);
+      L.fixed = nullptr;
+      return st;
+    }
+    L.owns = true;
+    FA_TRY(build_level_image(P, P->in_fixed, L.fixed, L, P->off_blur[i]));
+    FA_TRY(build_level_image(P, P->in_moving, L.moving, L, P->off_blur[i]));
+  }
+
+  // State: phi = id, m = v = 0, t = 0.
+  const int64_t n0 = P->levels[0].n;
+  FA_HIP(fa::launch_fill(P->d, 0.0f, 3 * n0, P->stream));
+  FA_HIP(fa::launch_fill(P->m, 0.0f, 3 * n0, P->stream));
+  FA_HIP(fa::launch_fill(P->v, 0.0f, 3 * n0, P->stream));
+  FA_HIP(fa::launch_fill(P->a, 0.0f, 3 * n0, P->stream));
+  FA_HIP(fa::launch_ctl_init(P->ctl, P->p.adam_beta1, P->p.adam_beta2, 0, 0, P->stream));
+  FA_HIP(fa::launch_mean(P->in_fixed, P->n, P->scratch, &P->ctl->shift_i, P->stream));
+  FA_HIP(fa::launch_mean(P->in_moving, P->n, P->scratch, &P->ctl->shift_j, P->stream));
+  P->cur_level = 0;
+  P->cur_iter = 0;
+  P->t_done = 0;
+  P->iters_done = 0;
+  P->scheduled = true;
+  return FA_OK;
+}
+
+fa_status fa_pair_step(fa_pair P, int max_iters, int* iters_done, int* finished) {
+  if (iters_done) *iters_done = 0;
+  if (finished) *finished = 0;
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  if (max_iters < 0) return fail(FA_EINVAL, "max_iters must be >= 0");
+  int done = 0;
+  while (done < max_iters) {
+    FA_TRY(advance_levels(P));
+    if (schedule_done(P)) break;
+    const Level& L = P->levels[P->cur_level];
+    FA_TRY(launch_iteration(P, L));
+    P->cur_iter += 1;
+    P->t_done += 1;
+    P->iters_done += 1;
+    done += 1;
+  }
+  if (iters_done) *iters_done = done;
+  if (finished) *finished = schedule_done(P) ? 1 : 0;
+  return FA_OK;
+}
+
+fa_status fa_pair_get_loss(fa_pair P, float* host_out, int capacity, int* n_written) {
+  if (n_written) *n_written = 0;
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!host_out && capacity > 0) return fail(FA_EINVAL, "host_out is NULL");
+  const int cnt = std::min(std::max(capacity, 0), P->scheduled ? std::min(P->iters_done, P->loss_cap) : 0);
+  FA_HIP(hipStreamSynchronize(P->stream));
+  if (cnt > 0) FA_HIP(hipMemcpy(host_out, P->loss_hist, (size_t)cnt * sizeof(float), hipMemcpyDeviceToHost));
+  if (n_written) *n_written = cnt;
+  return FA_OK;
+}
+
+fa_status fa_pair_get_field(fa_pair P, float* dev_out, int layout, int* level, fa_shape* shape) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  if (layout != 0 && layout != 1) return fail(FA_EINVAL, "layout must be 0 (SoA) or 1 (AoS)");
+  const Level& L = P->levels[P->cur_level];
+  if (level) *level = P->cur_level;
+  if (shape) *shape = L.shape;
+  if (!dev_out) return FA_OK;
+  if (layout == 0)
+    FA_HIP(hipMemcpyAsync(dev_out, P->d, (size_t)3 * L.n * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+  else
+    FA_HIP(fa::launch_soa_to_aos(P->d, dev_out, L.n, P->stream));
+  return FA_OK;
+}
+
+fa_status fa_pair_get_warped(fa_pair P, float* dev_out) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!dev_out) return fail(FA_EINVAL, "dev_out is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  const Level& L = P->levels[P->cur_level];
+  FA_HIP(fa::launch_warp(L.moving, P->d, dev_out, L.shape.n0, L.shape.n1, L.shape.n2, P->stream));
+  return FA_OK;
+}
+
+void fa_pair_destroy(fa_pair P) {
+  if (!P) return;
+  (void)hipStreamSynchronize(P->stream);
+  for (auto& pe : P->pending)
+    for (int k = 0; k < 5; ++k) P->ev_pool.push_back(pe.e[k]);
+  for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
+  free_all(P);
+  delete P;
+}
+
+// ---- fa_inspect.h ---------------------------------------------------------
+
+fa_status fa_pair_get_progress(fa_pair P, int* level, int* iter_in_level, int* t_done) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (level) *level = P->cur_level;
+  if (iter_in_level) *iter_in_level = P->cur_iter;
+  if (t_done) *t_done = P->t_done;
+  return FA_OK;
+}
+
+fa_status fa_pair_set_state(fa_pair P, const float* d, const float* m, const float* v, int t_done) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  if (t_done < 0 || t_done > (1 << 30)) return fail(FA_EINVAL, "t_done out of range");
+  const Level& L = P->levels[P->cur_level];
+  const size_t bytes = (size_t)3 * L.n * sizeof(float);
+  if (d) FA_HIP(hipMemcpyAsync(P->d, d, bytes, hipMemcpyDeviceToDevice, P->stream));
+  if (m) FA_HIP(hipMemcpyAsync(P->m, m, bytes, hipMemcpyDeviceToDevice, P->stream));
+  if (v) FA_HIP(hipMemcpyAsync(P->v, v, bytes, hipMemcpyDeviceToDevice, P->stream));
+  FA_HIP(fa::launch_ctl_init(P->ctl, P->p.adam_beta1, P->p.adam_beta2, t_done, -1, P->stream));
+  P->t_done = t_done;
+  return FA_OK;
+}
+
+fa_status fa_pair_get_state(fa_pair P, float* d, float* m, float* v) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  const Level& L = P->levels[P->cur_level];
+  const size_t bytes = (size_t)3 * L.n * sizeof(float);
+  if (d) FA_HIP(hipMemcpyAsync(d, P->d, bytes, hipMemcpyDeviceToDevice, P->stream));
+  if (m) FA_HIP(hipMemcpyAsync(m, P->m, bytes, hipMemcpyDeviceToDevice, P->stream));
+  if (v) FA_HIP(hipMemcpyAsync(v, P->v, bytes, hipMemcpyDeviceToDevice, P->stream));
+  return FA_OK;
+}
+
+fa_status fa_pair_eval_gradient(fa_pair P, float* g_dev, float* loss_host) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  const Level& L = P->levels[P->cur_level];
+  fa::GradArgs ga{};
+  ga.fixed = L.fixed;
+  ga.moving = L.moving;
+  ga.d = P->d;
+  ga.out = g_dev ? g_dev : P->tmp;
+  ga.partials = P->partials;
+  ga.ctl = P->ctl;
+  ga.n0 = L.shape.n0;
+  ga.n1 = L.shape.n1;
+  ga.n2 = L.shape.n2;
+  ga.zc = L.tg.zc;
+  ga.tiles_y = L.tg.tiles_y;
+  ga.tiles_x = L.tg.tiles_x;
+  ga.eps_cc = P->p.cc_eps;
+  ga.inv_n = (float)(1.0 / (double)L.n);
+  ga.mode = 1;
+  FA_HIP(fa::launch_grad(ga, P->p.cc_window, L.tg, P->stream));
+  if (loss_host) {
+    FA_HIP(fa::launch_sum_partials(P->partials, L.tg.blocks(), P->scratch + fa::kMeanBlocks, P->stream));
+    double s = 0.0;
+    FA_HIP(hipMemcpyAsync(&s, P->scratch + fa::kMeanBlocks, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    FA_HIP(hipStreamSynchronize(P->stream));
+    *loss_host = (float)(-s / (double)L.n);
+  }
+  return FA_OK;
+}
+
+fa_status fa_pair_get_direction(fa_pair P, float* dev_out) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!dev_out) return fail(FA_EINVAL, "dev_out is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  const Level& L = P->levels[P->cur_level];
+  FA_HIP(hipMemcpyAsync(dev_out, P->a, (size_t)3 * L.n * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+  return FA_OK;
+}
+
+fa_status fa_pair_get_step_norm(fa_pair P, float* m_host) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!m_host) return fail(FA_EINVAL, "m_host is NULL");
+  Ctl c;
+  FA_HIP(hipMemcpyAsync(&c, P->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
+  FA_HIP(hipStreamSynchronize(P->stream));
+  std::memcpy(m_host, &c.mbits, sizeof(float));
+  return FA_OK;
+}
+
+fa_status fa_pair_get_level_image(fa_pair P, int level, int which, float* dev_out, fa_shape* shape) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  if (level < 0 || level >= (int)P->levels.size()) return fail(FA_EINVAL, "level out of range");
+  if (which != 0 && which != 1) return fail(FA_EINVAL, "which must be 0 (fixed) or 1 (moving)");
+  const Level& L = P->levels[level];
+  if (shape) *shape = L.shape;
+  if (!dev_out) return FA_OK;
+  FA_HIP(hipMemcpyAsync(dev_out, which ? L.moving : L.fixed, (size_t)L.n * sizeof(float),
+                        hipMemcpyDeviceToDevice, P->stream));
+  return FA_OK;
+}
+
+fa_status fa_pair_profile(fa_pair P, int enable) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  FA_TRY(drain_profile(P));
+  P->profiling = enable != 0;
+  if (P->profiling) {
+    P->prof_ms.assign((size_t)16 * 4, 0.0);
+    P->prof_n.assign((size_t)16 * 4, 0);
+  }
+  return FA_OK;
+}
+
+fa_status fa_pair_get_profile(fa_pair P, int level, int kind, double* total_ms, int* launches) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (level < 0 || level >= 16 || kind < 0 || kind > 3) return fail(FA_EINVAL, "level or kind out of range");
+  FA_TRY(drain_profile(P));
+  const size_t slot = (size_t)level * 4 + kind;
+  if (total_ms) *total_ms = slot < P->prof_ms.size() ? P->prof_ms[slot] : 0.0;
+  if (launches) *launches = slot < P->prof_n.size() ? P->prof_n[slot] : 0;
+  return FA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Every case feeds the same seeded float32 inputs to the library and (promoted
+to float64) to the oracle, then compares element by element.  Tolerances
+(relative, as defined for this build):
+
+* warped intensity: max|dJ| / max|J|  <= 1e-5
+* loss:             |dL| / |L|        <= 1e-5
+* gradients and the quantities computed from them (Adam moments and
+  direction, smoothed steps, updated displacement): ||d||_2 / ||ref||_2 <= 1e-4
+* full run: mean endpoint difference <= 0.05 voxel
+
+Shapes span several in-plane tiles with ragged tails in both tiled axes, and
+n0 chunks with a ragged last chunk.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_01249_amd import Pair, fa, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL_J = 1e-5
+TOL_L = 1e-5
+TOL_G = 1e-4
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, ref):
+    return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def make_problem(shape, seed, field_max=2.0):
+    p = synth.blobs_pair(shape, seed=seed, n_blobs=12, sigma_range=(2.0, 5.0), field_sigma=3.0,
+                         field_max=field_max)
+    d = synth.smooth_field(shape, seed + 1000, sigma=3.0, max_norm=1.5)
+    return p.fixed, p.moving, d
+
+
+def new_pair(fixed, moving, **kw):
+    pr = Pair(dev(fixed), dev(moving), **kw)
+    return pr
+
+
+SHAPES = [(21, 37, 45), (12, 131, 133), (7, 5, 6)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_warp_identity_shift_and_random(shape):
+    fixed, moving, d = make_problem(shape, seed=11)
+    pr = new_pair(fixed, moving)
+    pr.set_schedule([1.0], [1])
+    zero = np.zeros((3,) + shape, np.float32)
+    pr.set_state(dev(zero), None, None, 0)
+    assert np.array_equal(host(pr.warped()), moving.astype(np.float64))          # identity: bitwise
+    shift = np.zeros_like(zero)
+    shift[0], shift[1], shift[2] = 1.0, -2.0, 3.0
+    pr.set_state(dev(shift), None, None, 0)
+    ref = O.warp_image(moving, shift)
+    assert np.array_equal(host(pr.warped()), ref)                                 # integer shift: exact
+    pr.set_state(dev(d), None, None, 0)
+    ref = O.warp_image(moving, d)
+    got = host(pr.warped())
+    assert np.abs(got - ref).max() / np.abs(ref).max() <= TOL_J
+    pr.close()
+
+
+@pytest.mark.parametrize("window", [1, 3, 5, 7, 9])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gradient_and_loss_match_oracle(shape, window):
+    fixed, moving, d = make_problem(shape, seed=21 + window)
+    pr = new_pair(fixed, moving, window=window)
+    pr.set_schedule([1.0], [1])
+    pr.set_state(dev(d), None, None, 0)
+    g, loss = pr.eval_gradient()
+    g_ref, L_ref = O.gateaux_gradient(fixed, moving, d, window, 1e-5)
+    assert abs(loss - L_ref) <= TOL_L * abs(L_ref)
+    assert rel_l2(host(g), g_ref) <= TOL_G
+    pr.close()
+
+
+@pytest.mark.parametrize("shape", [(21, 37, 45), (12, 131, 133)])
+def test_one_iteration_from_injected_state(shape):
+    """Every intermediate of one iteration of Algorithm 1 from the same state."""
+    fixed, moving, d = make_problem(shape, seed=31)
+    rng = np.random.default_rng(32)
+    m = (1e-6 * rng.standard_normal((3,) + shape)).astype(np.float32)
+    v = (1e-12 * rng.random((3,) + shape)).astype(np.float32)
+    t_done = 7
+    P = O.Params(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5)
+    pr = new_pair(fixed, moving, eta=P.eta, sigma_grad=P.sigma_grad, sigma_warp=P.sigma_warp, window=5)
+    pr.set_schedule([1.0], [1])
+    pr.set_state(dev(d), dev(m), dev(v), t_done)
+    pr.step(1)
+    d1, m1, v1 = (host(x) for x in pr.state())
+    a = host(pr.direction())
+    M = pr.step_norm()
+    loss = pr.loss_history()
+    ref_d, ref_m, ref_v, ref_L, ex = O.iterate(fixed, moving, d.astype(np.float64), m.astype(np.float64),
+                                               v.astype(np.float64), t_done + 1, P)
+    assert len(loss) == 1
+    assert abs(loss[-1] - ref_L) <= TOL_L * abs(ref_L)
+    assert rel_l2(m1, ref_m) <= TOL_G
+    assert rel_l2(v1, ref_v) <= TOL_G
+    assert rel_l2(a, ex["a"]) <= TOL_G
+    assert abs(M - ex["M"]) <= TOL_G * ex["M"]
+    assert rel_l2(d1 - d, ref_d - d) <= TOL_G       # the update itself, not just d
+    assert np.abs(d1 - ref_d).max() <= 1e-4
+    pr.close()
+
+
+def test_first_iteration_moves_at_most_eta_over_two():
+    fixed, moving, _ = make_problem((21, 37, 45), seed=41)
+    pr = new_pair(fixed, moving, eta=0.5, sigma_grad=1.0, sigma_warp=0.0)
+    pr.set_schedule([1.0], [1])
+    pr.step(1)
+    d = host(pr.field())
+    assert np.sqrt((d ** 2).sum(0)).max() == pytest.approx(0.25, rel=1e-5)
+    pr.close()
+
+
+@pytest.mark.parametrize("shape,scales", [((48, 56, 40), [4.0, 2.0, 1.0]), ((23, 19, 37), [2.0, 1.0]),
+                                          ((33, 64, 70), [3.0, 1.5])])
+def test_pyramid_levels_match_oracle(shape, scales):
+    p = synth.tissue_pair(shape, seed=51, bias_sigma=6.0, field_sigma=4.0, field_max=2.0)
+    pr = new_pair(p.fixed, p.moving)
+    pr.set_schedule(scales, [1] * len(scales))
+    for lvl, s in enumerate(scales):
+        for which, img in ((0, p.fixed), (1, p.moving)):
+            got = host(pr.level_image(lvl, which))
+            ref = O.downsample_image(img, s)
+            assert got.shape == ref.shape == O.level_shape(shape, s)
+            assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    pr.close()
+
+
+def test_level_transition_upsamples_state():
+    shape = (24, 30, 34)
+    fixed, moving, _ = make_problem(shape, seed=61)
+    pr = new_pair(fixed, moving)
+    pr.set_schedule([2.0, 1.0], [0, 0])
+    cshape = O.level_shape(shape, 2.0)
+    rng = np.random.default_rng(62)
+    d = synth.smooth_field(cshape, 63, sigma=2.0, max_norm=1.0)
+    m = rng.standard_normal((3,) + cshape).astype(np.float32)
+    v = rng.random((3,) + cshape).astype(np.float32)
+    pr.set_state(dev(d), dev(m), dev(v), 3)
+    done, fin = pr.step(1)
+    assert done == 0 and fin == 1
+    assert pr.progress()[0] == 1
+    d2, m2, v2 = (host(x) for x in pr.state())
+    rd, rm, rv = O.upsample_state(d.astype(np.float64), m.astype(np.float64), v.astype(np.float64), shape)
+    for got, ref in ((d2, rd), (m2, rm), (v2, rv)):
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    pr.close()
+
+
+def _full_run(name):
+    p = synth.load(name)
+    gold = np.load(os.path.join(HERE, "golden", f"{name}_oracle.npz"), allow_pickle=False)
+    pr = new_pair(p.fixed, p.moving, eta=float(gold["eta"]), sigma_grad=float(gold["sigma_grad"]),
+                  sigma_warp=float(gold["sigma_warp"]), window=int(gold["window"]))
+    pr.set_schedule(list(gold["scales"]), [int(i) for i in gold["iters"]])
+    done = pr.run()
+    assert done == int(np.sum(gold["iters"]))
+    return p, gold, pr
+
+
+def test_full_run_blobs64_matches_oracle():
+    """Whole 64^3 two-level run against the stored oracle run.  The bound is
+    the mean endpoint difference (0.05 voxel); the loss trajectory is also
+    held close (fp32 and fp64 trajectories separate slowly once the
+    fixed-length steps of Appendix E oscillate around the optimum)."""
+    p, gold, pr = _full_run("blobs64")
+    loss = pr.loss_history().astype(np.float64)
+    ref = gold["losses"]
+    assert loss.shape == ref.shape
+    s = int(gold["field_stride"])
+    d = host(pr.field())[:, ::s, ::s, ::s]
+    epe = float(np.sqrt(((d - gold["field"]) ** 2).sum(0)).mean())
+    rel = np.abs(loss - ref) / np.abs(ref)
+    print(f"full run: mean endpoint diff {epe:.4f} vox; loss rel diff first {rel[0]:.2e}, "
+          f"level-0 max {rel[:100].max():.2e}, overall max {rel.max():.2e}")
+    assert rel[0] <= TOL_L              # same state, same cost
+    assert epe <= 0.05
+    assert rel.max() <= 1e-2
+    pr.close()
+
+
+def test_runs_are_bitwise_deterministic():
+    fixed, moving, _ = make_problem((21, 37, 45), seed=71)
+    hist = []
+    for _ in range(2):
+        pr = new_pair(fixed, moving)
+        pr.set_schedule([2.0, 1.0], [6, 4])
+        pr.run()
+        hist.append((pr.loss_history(), host(pr.field())))
+        pr.close()
+    assert np.array_equal(hist[0][0], hist[1][0])
+    assert np.array_equal(hist[0][1], hist[1][1])
+
+
+def test_step_before_schedule_is_a_state_error():
+    fixed, moving, _ = make_problem((8, 9, 10), seed=81)
+    pr = new_pair(fixed, moving)
+    with pytest.raises(fa.FAError) as e:
+        pr.step(1)
+    assert e.value.status == fa.FA_ESTATE
+    pr.set_schedule([1.0], [2])
+    assert pr.step(5) == (2, 1)
+    assert pr.step(5) == (0, 1)
+    pr.close()
