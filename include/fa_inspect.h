@@ -60,6 +60,16 @@ fa_status fa_pair_get_level_image(fa_pair pair, int level, int which, float* dev
 fa_status fa_pair_profile(fa_pair pair, int enable);
 fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_ms, int* launches);
 
+/* Launch-shape override for tuning.  kind 0 = gradient kernel, 1 = the two
+ * sigma_grad smoothing kernels, 2 = the sigma_warp smoothing kernel.  ty x tx
+ * is the in-plane tile (n1 x n2): 16x32, 8x32 or 8x64, or 0x0 for the
+ * automatic choice; zc is the number of n0 planes per workgroup (0 =
+ * automatic); variant selects the gradient kernel's schedule (0 automatic,
+ * 1 next-plane gathers overlapped with the LDS passes, 2 issued after them).
+ * Takes effect at the next fa_pair_set_schedule.  Results do not depend on
+ * the launch shape beyond floating-point summation order. */
+fa_status fa_pair_set_tuning(fa_pair pair, int kind, int ty, int tx, int zc, int variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ struct Ctl {
 struct Tiling {
   int ty, tx, zc;
   int tiles_y, tiles_x, chunks;
+  int variant = 0;   // gradient kernel: 2 = gathers issued after the LDS passes
   int blocks() const { return tiles_y * tiles_x * chunks; }
 };
 

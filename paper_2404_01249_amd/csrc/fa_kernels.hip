@@ -183,8 +183,108 @@ __device__ float block_max(float v, float* red) {
 // the per-centre coefficients A, B, C) runs on the tile plus an r halo:
 // in-plane passes first, then a register ring along n0.  The output plane
 // lags the input plane by 2r.
+//
+// Every thread's first stage-1 column is its own output column, so the
+// output stage finds I, J and grad_p I_m at its plane in the oldest ring
+// entries instead of sampling the moving image a second time.  The loads and
+// gathers of the next input plane, and the Adam moments of the next output
+// plane, are issued before the current plane's LDS passes and consumed after
+// them (a two-stage software pipeline across the barriers).
 // ---------------------------------------------------------------------------
-template <int W, int TY, int TX>
+
+// Eight corner values of a trilinear sample in flight, with the fraction and
+// a validity mask; the mask is applied when the values are consumed so that
+// issuing the loads does not wait for them.
+struct Gather {
+  float c[8];
+  float t0, t1, t2;
+  unsigned mask;
+};
+
+__device__ __forceinline__ void gather_issue(const float* __restrict__ f, const Corners& c, Gather& g) {
+  const bool ok[8] = {c.a0 && c.a1 && c.a2, c.a0 && c.a1 && c.b2, c.a0 && c.b1 && c.a2, c.a0 && c.b1 && c.b2,
+                      c.b0 && c.a1 && c.a2, c.b0 && c.a1 && c.b2, c.b0 && c.b1 && c.a2, c.b0 && c.b1 && c.b2};
+  const int off[8] = {0, 1, c.s1, c.s1 + 1, c.s0, c.s0 + 1, c.s0 + c.s1, c.s0 + c.s1 + 1};
+  unsigned m = 0u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    g.c[k] = f[ok[k] ? c.base + off[k] : 0];
+    m |= (ok[k] ? 1u : 0u) << k;
+  }
+  g.mask = m;
+  g.t0 = c.t0;
+  g.t1 = c.t1;
+  g.t2 = c.t2;
+}
+
+__device__ __forceinline__ float gather_value(const Gather& g) {
+  float v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = ((g.mask >> k) & 1u) ? g.c[k] : 0.0f;
+  const float e00 = v[0] + g.t2 * (v[1] - v[0]);
+  const float e01 = v[2] + g.t2 * (v[3] - v[2]);
+  const float e10 = v[4] + g.t2 * (v[5] - v[4]);
+  const float e11 = v[6] + g.t2 * (v[7] - v[6]);
+  const float f0 = e00 + g.t1 * (e01 - e00);
+  const float f1 = e10 + g.t1 * (e11 - e10);
+  return f0 + g.t0 * (f1 - f0);
+}
+
+__device__ __forceinline__ float gather_value_grad(const Gather& g, float& g0, float& g1, float& g2) {
+  float v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = ((g.mask >> k) & 1u) ? g.c[k] : 0.0f;
+  const float dx00 = v[1] - v[0], dx01 = v[3] - v[2], dx10 = v[5] - v[4], dx11 = v[7] - v[6];
+  const float e00 = v[0] + g.t2 * dx00;
+  const float e01 = v[2] + g.t2 * dx01;
+  const float e10 = v[4] + g.t2 * dx10;
+  const float e11 = v[6] + g.t2 * dx11;
+  const float dy0 = e01 - e00, dy1 = e11 - e10;
+  const float f0 = e00 + g.t1 * dy0;
+  const float f1 = e10 + g.t1 * dy1;
+  const float dxy0 = dx00 + g.t1 * (dx01 - dx00);
+  const float dxy1 = dx10 + g.t1 * (dx11 - dx10);
+  g0 = f1 - f0;
+  g1 = dy0 + g.t0 * (dy1 - dy0);
+  g2 = dxy0 + g.t0 * (dxy1 - dxy0);
+  return f0 + g.t0 * (f1 - f0);
+}
+
+// Stage-1 column `slot` of thread `tid` as (row, column) of the halo tile.
+// Slot 0 is the thread's own output column; the remaining slots enumerate
+// the halo bands (top, bottom, left, right).
+template <int TY, int TX, int H>
+__device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex) {
+  constexpr int NT = TY * TX;
+  constexpr int EX = TX + 2 * H;
+  if (slot == 0) {
+    ey = H + tid / TX;
+    ex = H + tid % TX;
+    return true;
+  }
+  const int h = tid + (slot - 1) * NT;
+  constexpr int TB = H * EX;       // one horizontal band
+  constexpr int LB = TY * H;       // one vertical band
+  if (h < TB) {
+    ey = h / EX;
+    ex = h % EX;
+  } else if (h < 2 * TB) {
+    ey = H + TY + (h - TB) / EX;
+    ex = (h - TB) % EX;
+  } else if (h < 2 * TB + LB) {
+    ey = H + (h - 2 * TB) / H;
+    ex = (h - 2 * TB) % H;
+  } else if (h < 2 * TB + 2 * LB) {
+    ey = H + (h - 2 * TB - LB) / H;
+    ex = H + TX + (h - 2 * TB - LB) % H;
+  } else {
+    ey = ex = 0;
+    return false;
+  }
+  return true;
+}
+
+template <int W, int TY, int TX, bool PIPE>
 __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   constexpr int R = W / 2;
   constexpr int NT = TY * TX;
@@ -192,7 +292,7 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   constexpr int E2Y = TY + 2 * R, E2X = TX + 2 * R, E2 = E2Y * E2X;
   constexpr int XS1 = E1Y * E2X;
   constexpr int XS2 = E2Y * TX;
-  constexpr int CPT1 = (E1 + NT - 1) / NT;
+  constexpr int CPT1 = 1 + (E1 - NT + NT - 1) / NT;   // own column + halo columns
   extern __shared__ float lds[];
   float* buf = lds;             // [5][E1], later [3][E2]
   float* bufx = lds + 5 * E1;   // [5][XS1], later [3][XS2]
@@ -210,26 +310,30 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   const int z1 = min(z0 + A.zc, n0);
   const int y0 = by * TY, x0 = bx * TX;
 
-  int cy[CPT1], cx[CPT1];
-  bool cin[CPT1];
+  int cy[CPT1], cx[CPT1], cl[CPT1];
+  bool cin[CPT1], cuse[CPT1];
 #pragma unroll
   for (int k = 0; k < CPT1; ++k) {
-    const int c = tid + k * NT;
-    cy[k] = y0 - 2 * R + c / E1X;
-    cx[k] = x0 - 2 * R + c % E1X;
-    cin[k] = (c < E1) && cy[k] >= 0 && cy[k] < n1 && cx[k] >= 0 && cx[k] < n2;
+    int ey, ex;
+    cuse[k] = slot_coords<TY, TX, 2 * R>(tid, k, ey, ex);
+    cl[k] = ey * E1X + ex;
+    cy[k] = y0 - 2 * R + ey;
+    cx[k] = x0 - 2 * R + ex;
+    cin[k] = cuse[k] && cy[k] >= 0 && cy[k] < n1 && cx[k] >= 0 && cx[k] < n2;
   }
   const int oy = tid / TX, ox = tid % TX;
   const int gy = y0 + oy, gx = x0 + ox;
-  const bool out_col = gy < n1 && gx < n2;
+  const bool out_col = gy < n1 && gx < n2;   // == cin[0]
 
   float ringI[CPT1][W], ringJ[CPT1][W];
+  float ringG0[W], ringG1[W], ringG2[W];   // grad_p I_m of the own column
   float ringA[W], ringB[W], ringC[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) {
 #pragma unroll
     for (int k = 0; k < CPT1; ++k) { ringI[k][j] = 0.0f; ringJ[k][j] = 0.0f; }
     ringA[j] = ringB[j] = ringC[j] = 0.0f;
+    ringG0[j] = ringG1[j] = ringG2[j] = 0.0f;
   }
 
   const float bc1 = A.ctl->bc1, bc2 = A.ctl->bc2;
@@ -237,176 +341,261 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
   double lacc = 0.0;
 
-  for (int zin = z0 - 2 * R; zin < z1 + 2 * R; ++zin) {
-    const bool zok = zin >= 0 && zin < n0;
+  const int zs = z0 - 2 * R, ze = z1 + 2 * R;
+
+  // pipeline registers: raw loads of plane z+1 and gathers in flight
+  float nd0[CPT1], nd1[CPT1], nd2[CPT1], nf[CPT1];
+  Gather gq[CPT1];
+  float curI[CPT1], curJ[CPT1], curG0 = 0.f, curG1 = 0.f, curG2 = 0.f;
+  float nxI[CPT1];
+  bool gv[CPT1];
+
+  auto load_raw = [&](int z, int k) {
+    if (z >= 0 && z < n0 && cin[k]) {
+      const int idx = vidx(z, cy[k], cx[k], n1, n2);
+      nd0[k] = A.d[idx];
+      nd1[k] = A.d[N + idx];
+      nd2[k] = A.d[2 * N + idx];
+      nf[k] = A.fixed[idx];
+    }
+  };
+  auto issue_gather = [&](int z, int k) {
+    gv[k] = z >= 0 && z < n0 && cin[k];
+    if (gv[k]) {
+      const Corners c = corners_at(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
+      gather_issue(A.moving, c, gq[k]);
+      nxI[k] = nf[k] - si;
+    }
+  };
+  auto finish_gather = [&](int k) {
+    if (gv[k]) {
+      if (k == 0) {
+        curJ[0] = gather_value_grad(gq[0], curG0, curG1, curG2) - sj;
+      } else {
+        curJ[k] = gather_value(gq[k]) - sj;
+      }
+      curI[k] = nxI[k];
+    } else {
+      curJ[k] = 0.0f;
+      curI[k] = 0.0f;
+      if (k == 0) curG0 = curG1 = curG2 = 0.0f;
+    }
+  };
+
+  // prologue: plane zs in registers, plane zs+1 raw loads in flight
+#pragma unroll
+  for (int k = 0; k < CPT1; ++k) {
+    load_raw(zs, k);
+    issue_gather(zs, k);
+    finish_gather(k);
+    load_raw(zs + 1, k);
+  }
+  float pm[3] = {0.f, 0.f, 0.f}, pv[3] = {0.f, 0.f, 0.f};
+  bool mv_ready = false;
+
+  for (int zin = zs; zin < ze; ++zin) {
 #pragma unroll
     for (int k = 0; k < CPT1; ++k) {
-      float iv = 0.0f, jv = 0.0f;
-      if (zok && cin[k]) {
-        const int idx = vidx(zin, cy[k], cx[k], n1, n2);
-        iv = A.fixed[idx] - si;
-        const Corners c = corners_at(n0, n1, n2, zin, cy[k], cx[k], A.d[idx], A.d[N + idx], A.d[2 * N + idx]);
-        jv = tri(A.moving, c) - sj;
-      }
 #pragma unroll
       for (int j = 0; j < W - 1; ++j) {
         ringI[k][j] = ringI[k][j + 1];
         ringJ[k][j] = ringJ[k][j + 1];
       }
-      ringI[k][W - 1] = iv;
-      ringJ[k][W - 1] = jv;
+      ringI[k][W - 1] = curI[k];
+      ringJ[k][W - 1] = curJ[k];
     }
-    if (zin < z0) continue;  // rings still filling; uniform across the workgroup
-
 #pragma unroll
-    for (int k = 0; k < CPT1; ++k) {
-      const int c = tid + k * NT;
-      if (c < E1) {
+    for (int j = 0; j < W - 1; ++j) {
+      ringG0[j] = ringG0[j + 1];
+      ringG1[j] = ringG1[j + 1];
+      ringG2[j] = ringG2[j + 1];
+    }
+    ringG0[W - 1] = curG0;
+    ringG1[W - 1] = curG1;
+    ringG2[W - 1] = curG2;
+    // next plane: gathers in flight during this plane's passes (PIPE), or
+    // issued after them (fewer live registers)
+    if (PIPE) {
+#pragma unroll
+      for (int k = 0; k < CPT1; ++k) {
+        issue_gather(zin + 1, k);
+        load_raw(zin + 2, k);
+      }
+    }
+
+    if (zin >= z0) {
+#pragma unroll
+      for (int k = 0; k < CPT1; ++k) {
+        if (cuse[k]) {
+          float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            const float i_ = ringI[k][j], j_ = ringJ[k][j];
+            s0 += i_;
+            s1 += j_;
+            s2 += i_ * i_;
+            s3 += j_ * j_;
+            s4 += i_ * j_;
+          }
+          const int c = cl[k];
+          buf[c] = s0;
+          buf[E1 + c] = s1;
+          buf[2 * E1 + c] = s2;
+          buf[3 * E1 + c] = s3;
+          buf[4 * E1 + c] = s4;
+        }
+      }
+      __syncthreads();
+      for (int c = tid; c < XS1; c += NT) {
+        const int yy = c / E2X, xo = c - yy * E2X;
+        const float* src = buf + yy * E1X + xo;
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
+        for (int k = 0; k < W; ++k) {
+          s0 += src[k];
+          s1 += src[E1 + k];
+          s2 += src[2 * E1 + k];
+          s3 += src[3 * E1 + k];
+          s4 += src[4 * E1 + k];
+        }
+        bufx[c] = s0;
+        bufx[XS1 + c] = s1;
+        bufx[2 * XS1 + c] = s2;
+        bufx[3 * XS1 + c] = s3;
+        bufx[4 * XS1 + c] = s4;
+      }
+      __syncthreads();
+      const int zc1 = zin - R;
+      const bool z1ok = zc1 >= 0 && zc1 < n0;
+      const float cz = clipped_count(zc1, n0, R);
+      const bool z1out = zc1 >= z0 && zc1 < z1;
+      for (int c = tid; c < E2; c += NT) {
+        const int yo = c / E2X, xo = c - yo * E2X;
+        const float* src = bufx + yo * E2X + xo;
+        float SI = 0.f, SJ = 0.f, SII = 0.f, SJJ = 0.f, SIJ = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          SI += src[k * E2X];
+          SJ += src[XS1 + k * E2X];
+          SII += src[2 * XS1 + k * E2X];
+          SJJ += src[3 * XS1 + k * E2X];
+          SIJ += src[4 * XS1 + k * E2X];
+        }
+        const int yy = y0 - R + yo, xx = x0 - R + xo;
+        float ca = 0.f, cb = 0.f, cc_ = 0.f;
+        // A one-voxel window has zero variance and zero covariance exactly, so
+        // its correlation and every coefficient are 0 (W == 1 skips the
+        // arithmetic that would leave rounding residue).
+        if (W > 1 && z1ok && yy >= 0 && yy < n1 && xx >= 0 && xx < n2) {
+          const float cnt = cz * clipped_count(yy, n1, R) * clipped_count(xx, n2, R);
+          const float muI = SI / cnt, muJ = SJ / cnt;
+          const float cross = SIJ - muI * SJ;
+          const float vI = SII - muI * SI;
+          const float vJ = SJJ - muJ * SJ;
+          const float D = vI * vJ + A.eps_cc;
+          if (D != 0.0f) {
+            const float invD = 1.0f / D;
+            const float cc = cross * cross * invD;
+            ca = 2.0f * cross * invD;
+            cb = -2.0f * cc * vI * invD;
+            cc_ = ca * muI + cb * muJ;
+            if (z1out && yo >= R && yo < R + TY && xo >= R && xo < R + TX) lacc += (double)cc;
+          }
+        }
+        buf[c] = ca;
+        buf[E2 + c] = cb;
+        buf[2 * E2 + c] = cc_;
+      }
+      __syncthreads();
+      for (int c = tid; c < XS2; c += NT) {
+        const int yy = c / TX, xo = c - yy * TX;
+        const float* src = buf + yy * E2X + xo;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          s0 += src[k];
+          s1 += src[E2 + k];
+          s2 += src[2 * E2 + k];
+        }
+        bufx[c] = s0;
+        bufx[XS2 + c] = s1;
+        bufx[2 * XS2 + c] = s2;
+      }
+      __syncthreads();
+      {
+        const float* src = bufx + oy * TX + ox;
+        float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          sa += src[k * TX];
+          sb += src[XS2 + k * TX];
+          sc += src[2 * XS2 + k * TX];
+        }
+#pragma unroll
+        for (int j = 0; j < W - 1; ++j) {
+          ringA[j] = ringA[j + 1];
+          ringB[j] = ringB[j + 1];
+          ringC[j] = ringC[j + 1];
+        }
+        ringA[W - 1] = sa;
+        ringB[W - 1] = sb;
+        ringC[W - 1] = sc;
+      }
+      const int zc2 = zc1 - R;
+      if (zc2 >= z0 && out_col) {
+        const int idx = vidx(zc2, gy, gx, n1, n2);
+        if (A.mode == 0 && !mv_ready) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            pm[q] = A.m[q * N + idx];
+            pv[q] = A.v[q * N + idx];
+          }
+        }
+        float SA = 0.f, SB = 0.f, SC = 0.f;
+#pragma unroll
         for (int j = 0; j < W; ++j) {
-          const float i_ = ringI[k][j], j_ = ringJ[k][j];
-          s0 += i_;
-          s1 += j_;
-          s2 += i_ * i_;
-          s3 += j_ * j_;
-          s4 += i_ * j_;
+          SA += ringA[j];
+          SB += ringB[j];
+          SC += ringC[j];
         }
-        buf[c] = s0;
-        buf[E1 + c] = s1;
-        buf[2 * E1 + c] = s2;
-        buf[3 * E1 + c] = s3;
-        buf[4 * E1 + c] = s4;
-      }
-    }
-    __syncthreads();
-    for (int c = tid; c < XS1; c += NT) {
-      const int yy = c / E2X, xo = c - yy * E2X;
-      const float* src = buf + yy * E1X + xo;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+        // oldest ring entries of the own column hold plane zc2
+        const float dl = -A.inv_n * (ringI[0][0] * SA + ringJ[0][0] * SB - SC);
+        const float g[3] = {dl * ringG0[0], dl * ringG1[0], dl * ringG2[0]};
+        if (A.mode == 0) {
+          const float b1 = A.beta1, b2 = A.beta2;
 #pragma unroll
-      for (int k = 0; k < W; ++k) {
-        s0 += src[k];
-        s1 += src[E1 + k];
-        s2 += src[2 * E1 + k];
-        s3 += src[3 * E1 + k];
-        s4 += src[4 * E1 + k];
-      }
-      bufx[c] = s0;
-      bufx[XS1 + c] = s1;
-      bufx[2 * XS1 + c] = s2;
-      bufx[3 * XS1 + c] = s3;
-      bufx[4 * XS1 + c] = s4;
-    }
-    __syncthreads();
-    const int zc1 = zin - R;
-    const bool z1ok = zc1 >= 0 && zc1 < n0;
-    const float cz = clipped_count(zc1, n0, R);
-    const bool z1out = zc1 >= z0 && zc1 < z1;
-    for (int c = tid; c < E2; c += NT) {
-      const int yo = c / E2X, xo = c - yo * E2X;
-      const float* src = bufx + yo * E2X + xo;
-      float SI = 0.f, SJ = 0.f, SII = 0.f, SJJ = 0.f, SIJ = 0.f;
+          for (int q = 0; q < 3; ++q) {
+            const int iq = q * N + idx;
+            const float mm = b1 * pm[q] + (1.0f - b1) * g[q];
+            const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
+            A.m[iq] = mm;
+            A.v[iq] = vv;
+            A.out[iq] = (mm / bc1) / (sqrtf(vv / bc2) + A.adam_eps);
+          }
+          // Adam moments of the next output plane
+          mv_ready = zc2 + 1 < z1;
+          if (mv_ready) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) {
-        SI += src[k * E2X];
-        SJ += src[XS1 + k * E2X];
-        SII += src[2 * XS1 + k * E2X];
-        SJJ += src[3 * XS1 + k * E2X];
-        SIJ += src[4 * XS1 + k * E2X];
-      }
-      const int yy = y0 - R + yo, xx = x0 - R + xo;
-      float ca = 0.f, cb = 0.f, cc_ = 0.f;
-      // A one-voxel window has zero variance and zero covariance exactly, so
-      // its correlation and every coefficient are 0 (W == 1 skips the
-      // arithmetic that would leave rounding residue).
-      if (W > 1 && z1ok && yy >= 0 && yy < n1 && xx >= 0 && xx < n2) {
-        const float cnt = cz * clipped_count(yy, n1, R) * clipped_count(xx, n2, R);
-        const float muI = SI / cnt, muJ = SJ / cnt;
-        const float cross = SIJ - muI * SJ;
-        const float vI = SII - muI * SI;
-        const float vJ = SJJ - muJ * SJ;
-        const float D = vI * vJ + A.eps_cc;
-        if (D != 0.0f) {
-          const float invD = 1.0f / D;
-          const float cc = cross * cross * invD;
-          ca = 2.0f * cross * invD;
-          cb = -2.0f * cc * vI * invD;
-          cc_ = ca * muI + cb * muJ;
-          if (z1out && yo >= R && yo < R + TY && xo >= R && xo < R + TX) lacc += (double)cc;
+            for (int q = 0; q < 3; ++q) {
+              pm[q] = A.m[q * N + idx + n1 * n2];
+              pv[q] = A.v[q * N + idx + n1 * n2];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) A.out[q * N + idx] = g[q];
         }
       }
-      buf[c] = ca;
-      buf[E2 + c] = cb;
-      buf[2 * E2 + c] = cc_;
     }
-    __syncthreads();
-    for (int c = tid; c < XS2; c += NT) {
-      const int yy = c / TX, xo = c - yy * TX;
-      const float* src = buf + yy * E2X + xo;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    if (!PIPE) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) {
-        s0 += src[k];
-        s1 += src[E2 + k];
-        s2 += src[2 * E2 + k];
-      }
-      bufx[c] = s0;
-      bufx[XS2 + c] = s1;
-      bufx[2 * XS2 + c] = s2;
-    }
-    __syncthreads();
-    {
-      const float* src = bufx + oy * TX + ox;
-      float sa = 0.f, sb = 0.f, sc = 0.f;
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        sa += src[k * TX];
-        sb += src[XS2 + k * TX];
-        sc += src[2 * XS2 + k * TX];
-      }
-#pragma unroll
-      for (int j = 0; j < W - 1; ++j) {
-        ringA[j] = ringA[j + 1];
-        ringB[j] = ringB[j + 1];
-        ringC[j] = ringC[j + 1];
-      }
-      ringA[W - 1] = sa;
-      ringB[W - 1] = sb;
-      ringC[W - 1] = sc;
-    }
-    const int zc2 = zc1 - R;
-    if (zc2 >= z0 && out_col) {
-      float SA = 0.f, SB = 0.f, SC = 0.f;
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        SA += ringA[j];
-        SB += ringB[j];
-        SC += ringC[j];
-      }
-      const int idx = vidx(zc2, gy, gx, n1, n2);
-      const float iv = A.fixed[idx] - si;
-      const Corners c = corners_at(n0, n1, n2, zc2, gy, gx, A.d[idx], A.d[N + idx], A.d[2 * N + idx]);
-      float d0, d1, d2;
-      const float jv = tri_grad(A.moving, c, d0, d1, d2) - sj;
-      const float dl = -A.inv_n * (iv * SA + jv * SB - SC);
-      const float g[3] = {dl * d0, dl * d1, dl * d2};
-      if (A.mode == 0) {
-        const float b1 = A.beta1, b2 = A.beta2;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const int iq = q * N + idx;
-          const float mm = b1 * A.m[iq] + (1.0f - b1) * g[q];
-          const float vv = b2 * A.v[iq] + (1.0f - b2) * g[q] * g[q];
-          A.m[iq] = mm;
-          A.v[iq] = vv;
-          A.out[iq] = (mm / bc1) / (sqrtf(vv / bc2) + A.adam_eps);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) A.out[q * N + idx] = g[q];
+      for (int k = 0; k < CPT1; ++k) {
+        issue_gather(zin + 1, k);
+        load_raw(zin + 2, k);
       }
     }
+#pragma unroll
+    for (int k = 0; k < CPT1; ++k) finish_gather(k);
   }
   const double tot = block_sum<NT>(lacc, red);
   if (tid == 0) A.partials[blockIdx.x] = tot;
@@ -415,7 +604,9 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
 // ---------------------------------------------------------------------------
 // Separable Gaussian (replicate boundary) on a 3-channel field, streaming.
 // In-plane passes over a clamped halo tile in LDS, then a register ring of
-// 2R+1 planes per output column along n0.
+// 2R+1 planes per output column along n0.  The next plane's loads are issued
+// before the current plane's passes; the composition epilogue issues its
+// gathers of d in one plane step and consumes them in the next.
 // ---------------------------------------------------------------------------
 template <int R, int TY, int TX, int EPI>
 __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
@@ -423,6 +614,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   constexpr int NT = TY * TX;
   constexpr int EY = TY + 2 * R, EX = TX + 2 * R, E = EY * EX;
   constexpr int XS = EY * TX;
+  constexpr int CPT = (E + NT - 1) / NT;
   extern __shared__ float lds[];
   float* buf = lds;           // [3][E]
   float* bufx = lds + 3 * E;  // [3][XS]
@@ -444,6 +636,18 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   const int gy = y0 + oy, gx = x0 + ox;
   const bool out_col = gy < n1 && gx < n2;
 
+  // clamped in-plane offsets of this thread's halo-tile columns
+  int coff[CPT];
+  bool cuse[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * NT;
+    cuse[k] = c < E;
+    const int yy = min(max(y0 - R + c / EX, 0), n1 - 1);
+    const int xx = min(max(x0 - R + c % EX, 0), n2 - 1);
+    coff[k] = yy * n2 + xx;
+  }
+
   float w[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) w[k] = A.wts[k];
@@ -458,16 +662,46 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   }
   float mx = 0.0f;
 
-  for (int zin = z0 - R; zin < z1 + R; ++zin) {
-    const int zs = min(max(zin, 0), n0 - 1);
-    for (int c = tid; c < E; c += NT) {
-      const int yy = min(max(y0 - R + c / EX, 0), n1 - 1);
-      const int xx = min(max(x0 - R + c % EX, 0), n2 - 1);
-      const int idx = vidx(zs, yy, xx, n1, n2);
-      buf[c] = A.in[idx];
-      buf[E + c] = A.in[N + idx];
-      buf[2 * E + c] = A.in[2 * N + idx];
+  const int plane = n1 * n2;
+  float pre[CPT][3];
+  auto load_plane = [&](int z) {
+    const int base = min(max(z, 0), n0 - 1) * plane;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (cuse[k]) {
+        const int idx = base + coff[k];
+        pre[k][0] = A.in[idx];
+        pre[k][1] = A.in[N + idx];
+        pre[k][2] = A.in[2 * N + idx];
+      }
     }
+  };
+
+  // composition gathers in flight (EPI_COMPOSE)
+  Gather cg[3];
+  float cu[3] = {0.f, 0.f, 0.f};
+  int cidx = -1;
+  auto finish_compose = [&]() {
+    if (cidx >= 0) {
+      A.out[cidx] = cu[0] + gather_value(cg[0]);
+      A.out[N + cidx] = cu[1] + gather_value(cg[1]);
+      A.out[2 * N + cidx] = cu[2] + gather_value(cg[2]);
+      cidx = -1;
+    }
+  };
+
+  load_plane(z0 - R);
+  for (int zin = z0 - R; zin < z1 + R; ++zin) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (cuse[k]) {
+        const int c = tid + k * NT;
+        buf[c] = pre[k][0];
+        buf[E + c] = pre[k][1];
+        buf[2 * E + c] = pre[k][2];
+      }
+    }
+    if (zin + 1 < z1 + R) load_plane(zin + 1);
     __syncthreads();
     for (int c = tid; c < XS; c += NT) {
       const int yy = c / TX, xo = c - yy * TX;
@@ -484,6 +718,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
       bufx[2 * XS + c] = s2;
     }
     __syncthreads();
+    if (EPI == EPI_COMPOSE) finish_compose();
     {
       const float* src = bufx + oy * TX + ox;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
@@ -519,15 +754,19 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
         A.out[2 * N + idx] = v2;
       } else if (EPI == EPI_MAXNORM) {
         mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
-      } else {  // EPI_COMPOSE
-        const float u0 = scale * v0, u1 = scale * v1, u2 = scale * v2;
-        const Corners c = corners_at(n0, n1, n2, zo, gy, gx, u0, u1, u2);
-        A.out[idx] = u0 + tri(A.d, c);
-        A.out[N + idx] = u1 + tri(A.d + N, c);
-        A.out[2 * N + idx] = u2 + tri(A.d + 2 * N, c);
+      } else {  // EPI_COMPOSE: d' = u + d(x + u); finished next plane step
+        cu[0] = scale * v0;
+        cu[1] = scale * v1;
+        cu[2] = scale * v2;
+        const Corners c = corners_at(n0, n1, n2, zo, gy, gx, cu[0], cu[1], cu[2]);
+        gather_issue(A.d, c, cg[0]);
+        gather_issue(A.d + N, c, cg[1]);
+        gather_issue(A.d + 2 * N, c, cg[2]);
+        cidx = idx;
       }
     }
   }
+  if (EPI == EPI_COMPOSE) finish_compose();
 
   if (EPI == EPI_MAXNORM) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
@@ -535,8 +774,8 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   }
   if (EPI == EPI_STORE_FINAL) {
     // The last workgroup to finish records the iteration's loss and advances
-    // the Adam step count; every workgroup of this launch has read nothing
-    // from the control block, so the update cannot race.
+    // the Adam step count; no workgroup of this launch reads the control
+    // block, so the update cannot race.
     __syncthreads();
     if (tid == 0) {
       __threadfence();
@@ -683,7 +922,10 @@ constexpr size_t gauss_lds() {
 template <int W, int TY, int TX>
 hipError_t grad_launch_t(const GradArgs& a, const Tiling& t, hipStream_t s) {
   constexpr size_t sh = grad_lds<W, TY, TX>();
-  k_grad<W, TY, TX><<<dim3(t.blocks()), dim3(TY * TX), sh, s>>>(a);
+  if (t.variant == 2)
+    k_grad<W, TY, TX, false><<<dim3(t.blocks()), dim3(TY * TX), sh, s>>>(a);
+  else
+    k_grad<W, TY, TX, true><<<dim3(t.blocks()), dim3(TY * TX), sh, s>>>(a);
   return hipGetLastError();
 }
 
@@ -729,8 +971,12 @@ hipError_t gauss_launch_tile(const GaussArgs& a, int radius, int epi, const Tili
 
 }  // namespace
 
-bool grad_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
-bool gauss_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
+bool grad_tile_supported(int ty, int tx) {
+  return (ty == 16 && tx == 32) || (ty == 8 && tx == 32) || (ty == 8 && tx == 64);
+}
+bool gauss_tile_supported(int ty, int tx) {
+  return (ty == 16 && tx == 32) || (ty == 8 && tx == 32) || (ty == 8 && tx == 64);
+}
 
 size_t grad_lds_bytes(int window, int ty, int tx) {
   const int R = window / 2;
@@ -744,12 +990,14 @@ size_t gauss_lds_bytes(int radius, int ty, int tx) {
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
   if (t.ty == 16 && t.tx == 32) return grad_launch_tile<16, 32>(a, window, t, s);
   if (t.ty == 8 && t.tx == 32) return grad_launch_tile<8, 32>(a, window, t, s);
+  if (t.ty == 8 && t.tx == 64) return grad_launch_tile<8, 64>(a, window, t, s);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
   if (t.ty == 16 && t.tx == 32) return gauss_launch_tile<16, 32>(a, radius, epilogue, t, s);
   if (t.ty == 8 && t.tx == 32) return gauss_launch_tile<8, 32>(a, radius, epilogue, t, s);
+  if (t.ty == 8 && t.tx == 64) return gauss_launch_tile<8, 64>(a, radius, epilogue, t, s);
   return hipErrorInvalidValue;
 }
 

@@ -59,12 +59,21 @@ std::vector<float> gaussian_taps(float sigma_f) {
 
 int tap_radius(float sigma) { return (int)(gaussian_taps(sigma).size() / 2); }
 
+struct Tuning {
+  int ty = 0, tx = 0, zc = 0, variant = 0;
+};
+
 // In-plane tile and n0 chunking of one streaming launch.  halo = planes of
 // look-ahead the kernel needs on each side of its chunk.
-Tiling choose_tiling(const fa_shape& s, int halo) {
+Tiling choose_tiling(const fa_shape& s, int halo, const Tuning& tu = Tuning()) {
   Tiling t;
   t.tx = 32;
   t.ty = (s.n1 * s.n2 >= 128 * 128) ? 16 : 8;
+  if (tu.ty > 0 && tu.tx > 0) {
+    t.ty = tu.ty;
+    t.tx = tu.tx;
+  }
+  t.variant = tu.variant;
   t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
   t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
   const int plane_tiles = t.tiles_y * t.tiles_x;
@@ -72,6 +81,7 @@ Tiling choose_tiling(const fa_shape& s, int halo) {
   int chunks = std::max(1, (target + plane_tiles - 1) / plane_tiles);
   int zc = (s.n0 + chunks - 1) / chunks;
   zc = std::max(zc, std::max(4, halo));
+  if (tu.zc > 0) zc = tu.zc;
   zc = std::min(zc, s.n0);
   t.zc = zc;
   t.chunks = (s.n0 + zc - 1) / zc;
@@ -126,6 +136,7 @@ struct fa_pair_s {
   std::vector<Pending> pending;
   std::vector<double> prof_ms;   // [level][kind]
   std::vector<int> prof_n;
+  Tuning tune[3];   // gradient, sigma_grad, sigma_warp launches
   int cur_level = 0, cur_iter = 0;
   int t_done = 0;      // Adam steps taken (set_state may change it)
   int iters_done = 0;  // schedule iterations run = losses recorded
@@ -432,9 +443,9 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     lv[i].n = voxels(lv[i].shape);
     if (lv[i].shape.n0 < 2 || lv[i].shape.n1 < 2 || lv[i].shape.n2 < 2)
       return fail(FA_ESHAPE, "level " + std::to_string(i) + " has a dimension < 2");
-    lv[i].tg = choose_tiling(lv[i].shape, 2 * r);
-    lv[i].tsg = choose_tiling(lv[i].shape, P->rg);
-    lv[i].tsw = choose_tiling(lv[i].shape, P->rw);
+    lv[i].tg = choose_tiling(lv[i].shape, 2 * r, P->tune[0]);
+    lv[i].tsg = choose_tiling(lv[i].shape, P->rg, P->tune[1]);
+    lv[i].tsw = choose_tiling(lv[i].shape, P->rw, P->tune[2]);
     total_iters += iters[i];
     nmax = std::max(nmax, lv[i].n);
     pmax = std::max(pmax, lv[i].tg.blocks());
@@ -696,6 +707,20 @@ fa_status fa_pair_get_level_image(fa_pair P, int level, int which, float* dev_ou
   if (!dev_out) return FA_OK;
   FA_HIP(hipMemcpyAsync(dev_out, which ? L.moving : L.fixed, (size_t)L.n * sizeof(float),
                         hipMemcpyDeviceToDevice, P->stream));
+  return FA_OK;
+}
+
+fa_status fa_pair_set_tuning(fa_pair P, int kind, int ty, int tx, int zc, int variant) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (kind < 0 || kind > 2) return fail(FA_EINVAL, "kind must be 0, 1 or 2");
+  const bool autotile = ty == 0 && tx == 0;
+  if (!autotile && !(kind == 0 ? fa::grad_tile_supported(ty, tx) : fa::gauss_tile_supported(ty, tx)))
+    return fail(FA_EINVAL, "unsupported tile shape");
+  if (zc < 0 || variant < 0 || variant > 2) return fail(FA_EINVAL, "zc must be >= 0 and variant in [0, 2]");
+  P->tune[kind].ty = ty;
+  P->tune[kind].tx = tx;
+  P->tune[kind].zc = zc;
+  P->tune[kind].variant = variant;
   return FA_OK;
 }
 

@@ -62,6 +62,7 @@ SIGNATURES = {
     "fa_pair_get_step_norm": (_I, [_P, _FP]),
     "fa_pair_get_level_image": (_I, [_P, _I, _I, _P, ctypes.POINTER(fa_shape)]),
     "fa_pair_profile": (_I, [_P, _I]),
+    "fa_pair_set_tuning": (_I, [_P, _I, _I, _I, _I, _I]),
     "fa_pair_get_profile": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_double), _IP]),
 }
 
@@ -215,3 +216,7 @@ def fa_pair_get_profile(pair: int, level: int, kind: int) -> tuple[float, int]:
     ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
     _check(load_library().fa_pair_get_profile(pair, int(level), int(kind), ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), n.value
+
+
+def fa_pair_set_tuning(pair: int, kind: int, ty: int = 0, tx: int = 0, zc: int = 0, variant: int = 0):
+    _check(load_library().fa_pair_set_tuning(pair, int(kind), int(ty), int(tx), int(zc), int(variant)))
