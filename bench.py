@@ -30,6 +30,28 @@ if ROOT not in sys.path:
 METRIC = "voxel-iters/sec @160×192×224 fused vs plain per-op GPU, same accuracy"
 HBM_PEAK_GBS = 8000.0
 GRAD_BYTES_PER_VOXEL = 80   # reads I_f, I_m, d(3), m(3), v(3); writes m(3), v(3), a(3); fp32
+KERNEL_SRC = os.path.join(ROOT, "paper_2404_01249_amd", "csrc", "fa_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_tissue160_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the gradient kernel at the finest level, from
+    the committed rocprofv3 counter summary, if it was taken on the current
+    kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def level_voxels(shape, scales, iters):
@@ -131,6 +153,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calib", action="store_true",
+                    help="first run a 256 MiB read + 256 MiB write elementwise kernel "
+                         "(reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the dense matching step of one registration is not "
@@ -144,6 +169,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calib:
+        x = torch.ones(64 * 1024 * 1024, device="cuda")
+        y = torch.empty_like(x)
+        torch.add(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
     p = synth.load(args.workload)
     params = dict(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=p.window)
     lv = level_voxels(p.fixed.shape, p.scales, p.iters)
@@ -174,7 +205,7 @@ def main():
                    "voxel_iters_per_step": vox_iters, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_grad (warp+LNCC+adjoint+Adam), finest level",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": GRAD_BYTES_PER_VOXEL * n_fin, "avg_launch_us": per_launch_ms * 1e3,
                      "launches": g_n},
         "steady_state_finest": {"us_per_iteration": iter_ms_fin * 1e3,

@@ -77,7 +77,7 @@ fa_status fa_params_default(fa_params* out);
  *   fixed_dev, moving_dev: device pointers to float32 volumes of `shape`;
  *     copied on `hip_stream` (stream order), so the caller may release them
  *     once that copy has run.
- *   shape: every dimension >= 2; 3*n0*n1*n2 < 2^31.
+ *   shape: every dimension >= 2; n0*n1*n2 < 2^29 (512^3 fits).
  *   p: parameters (copied).  hip_stream: a hipStream_t (NULL = null stream).
  *   out: receives the handle.  Nothing is allocated on failure. */
 fa_status fa_pair_create(const float* fixed_dev, const float* moving_dev, fa_shape shape,

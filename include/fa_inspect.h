@@ -62,8 +62,8 @@ fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_m
 
 /* Launch-shape override for tuning.  kind 0 = gradient kernel, 1 = the two
  * sigma_grad smoothing kernels, 2 = the sigma_warp smoothing kernel.  ty x tx
- * is the in-plane tile (n1 x n2): 16x32, 8x32 or 8x64, or 0x0 for the
- * automatic choice; zc is the number of n0 planes per workgroup (0 =
+ * is the in-plane tile (n1 x n2): 16x32 or 8x32 for every kind, 8x64 also for
+ * kinds 1 and 2, or 0x0 for the automatic choice; zc is the number of n0 planes per workgroup (0 =
  * automatic); variant selects the gradient kernel's schedule (0 automatic,
  * 1 next-plane gathers overlapped with the LDS passes, 2 issued after them).
  * Takes effect at the next fa_pair_set_schedule.  Results do not depend on

@@ -51,7 +51,10 @@ struct GradArgs {
 };
 
 // ---- streaming separable Gaussian on a 3-channel field ---------------------
-enum GaussEpilogue { EPI_STORE = 0, EPI_MAXNORM = 1, EPI_COMPOSE = 2, EPI_STORE_FINAL = 3 };
+// EPI_COMPOSE samples d with global gathers (any step length);
+// EPI_COMPOSE_LDS stages three planes of d in LDS and needs |u| <= 1 voxel
+// (eta <= 2, since max |u| = eta / 2).
+enum GaussEpilogue { EPI_STORE = 0, EPI_MAXNORM = 1, EPI_COMPOSE = 2, EPI_STORE_FINAL = 3, EPI_COMPOSE_LDS = 4 };
 
 struct GaussArgs {
   const float* in;       // [3][N]

@@ -144,6 +144,16 @@ __device__ __forceinline__ float clipped_count(int i, int n, int r) {
   return (float)(min(i + r, n - 1) - max(i - r, 0) + 1);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumber them so that every XCD works through a contiguous range of
+// tiles: neighbouring tiles then share their halo reads in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  constexpr int X = 8;
+  const int q = G / X, r = G % X;
+  const int x = b % X, k = b / X;
+  return x * q + min(x, r) + k;
+}
+
 template <int NT>
 __device__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -192,26 +202,72 @@ __device__ float block_max(float v, float* red) {
 // them (a two-stage software pipeline across the barriers).
 // ---------------------------------------------------------------------------
 
-// Eight corner values of a trilinear sample in flight, with the fraction and
-// a validity mask; the mask is applied when the values are consumed so that
-// issuing the loads does not wait for them.
-struct Gather {
-  float c[8];
-  float t0, t1, t2;
+// Trilinear gathers as 32-bit byte offsets from a uniform base pointer (the
+// global loads then take the scalar-base form, with no per-lane 64-bit address
+// arithmetic).  Every offset stays inside the volume (an axis whose corner is
+// off the grid contributes offset 0), and an 8-bit mask zeroes the off-grid
+// corners when the values are consumed.
+__device__ __forceinline__ float load_at(const float* __restrict__ base, unsigned byte_off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (size_t)byte_off);
+}
+
+__device__ __forceinline__ void axis_offsets(int x, float dd, int n, int stride_bytes, unsigned& lo,
+                                             unsigned& hi, bool& lo_ok, bool& hi_ok, float& t) {
+  dd = fminf(fmaxf(dd, (float)(-x - 2)), (float)(n + 1 - x));
+  const float f = floorf(dd);
+  const int i = x + (int)f;
+  t = dd - f;
+  lo_ok = i >= 0 && i < n;
+  hi_ok = i >= -1 && i + 1 < n;
+  lo = lo_ok ? (unsigned)(i * stride_bytes) : 0u;
+  hi = hi_ok ? (unsigned)((i + 1) * stride_bytes) : 0u;
+}
+
+// The 8 corner offsets, validity mask and fractions of the sample at grid
+// point (z, y, x) displaced by (d0, d1, d2); the cell is x + floor(d) as in
+// cell_at.
+struct Cell8 {
+  unsigned off[8];
   unsigned mask;
+  float t0, t1, t2;
 };
 
-__device__ __forceinline__ void gather_issue(const float* __restrict__ f, const Corners& c, Gather& g) {
-  const bool ok[8] = {c.a0 && c.a1 && c.a2, c.a0 && c.a1 && c.b2, c.a0 && c.b1 && c.a2, c.a0 && c.b1 && c.b2,
-                      c.b0 && c.a1 && c.a2, c.b0 && c.a1 && c.b2, c.b0 && c.b1 && c.a2, c.b0 && c.b1 && c.b2};
-  const int off[8] = {0, 1, c.s1, c.s1 + 1, c.s0, c.s0 + 1, c.s0 + c.s1, c.s0 + c.s1 + 1};
-  unsigned m = 0u;
+__device__ __forceinline__ Cell8 cell8_at(int n0, int n1, int n2, int z, int y, int x, float d0, float d1,
+                                          float d2) {
+  Cell8 c;
+  unsigned l0, h0, l1, h1, l2, h2;
+  bool a0, b0, a1, b1, a2, b2;
+  axis_offsets(z, d0, n0, n1 * n2 * 4, l0, h0, a0, b0, c.t0);
+  axis_offsets(y, d1, n1, n2 * 4, l1, h1, a1, b1, c.t1);
+  axis_offsets(x, d2, n2, 4, l2, h2, a2, b2, c.t2);
+  const unsigned a00 = l0 + l1, a01 = l0 + h1, a10 = h0 + l1, a11 = h0 + h1;
+  c.off[0] = a00 + l2;
+  c.off[1] = a00 + h2;
+  c.off[2] = a01 + l2;
+  c.off[3] = a01 + h2;
+  c.off[4] = a10 + l2;
+  c.off[5] = a10 + h2;
+  c.off[6] = a11 + l2;
+  c.off[7] = a11 + h2;
+  const unsigned mz = (a0 ? 0x0Fu : 0u) | (b0 ? 0xF0u : 0u);
+  const unsigned my = (a1 ? 0x33u : 0u) | (b1 ? 0xCCu : 0u);
+  const unsigned mx = (a2 ? 0x55u : 0u) | (b2 ? 0xAAu : 0u);
+  c.mask = mz & my & mx;
+  return c;
+}
+
+// Eight corner values of a trilinear sample (loaded; consumed later so that
+// issuing the loads does not wait for them).
+struct Gather {
+  float c[8];
+  unsigned mask;
+  float t0, t1, t2;
+};
+
+__device__ __forceinline__ void gather_issue(const float* __restrict__ f, const Cell8& c, Gather& g) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    g.c[k] = f[ok[k] ? c.base + off[k] : 0];
-    m |= (ok[k] ? 1u : 0u) << k;
-  }
-  g.mask = m;
+  for (int k = 0; k < 8; ++k) g.c[k] = load_at(f, c.off[k]);
+  g.mask = c.mask;
   g.t0 = c.t0;
   g.t1 = c.t1;
   g.t2 = c.t2;
@@ -285,7 +341,7 @@ __device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex)
 }
 
 template <int W, int TY, int TX, bool PIPE>
-__global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
+__device__ __forceinline__ void grad_body(const GradArgs& A) {
   constexpr int R = W / 2;
   constexpr int NT = TY * TX;
   constexpr int E1Y = TY + 4 * R, E1X = TX + 4 * R, E1 = E1Y * E1X;
@@ -296,10 +352,23 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   extern __shared__ float lds[];
   float* buf = lds;             // [5][E1], later [3][E2]
   float* bufx = lds + 5 * E1;   // [5][XS1], later [3][XS2]
+  // grad_p I_m of the own column, delayed 2r planes from the input plane
+  // to the output plane: a per-thread delay line of GS slots in LDS (slot
+  // z mod GS).  Each thread touches only its own entries, so no barrier is
+  // involved; with r > 0 a plane is stored after the output stage has read
+  // the slot it replaces.
+  constexpr int GS = (R == 0) ? 1 : 2 * R;
+  // in LDS while the kernel's LDS stays within 64 KiB, else in registers
+  constexpr bool GLDS = sizeof(float) * (5 * E1 + 5 * XS1 + 3 * GS * NT) <= 65536;
+  float* gring = lds + 5 * E1 + 5 * XS1;   // [GS][3][NT] when GLDS
+  float greg[3][GS];                       // when !GLDS: oldest entry first
+#pragma unroll
+  for (int j = 0; j < GS; ++j) greg[0][j] = greg[1][j] = greg[2][j] = 0.0f;
+
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
-  int b = blockIdx.x;
+  int b = xcd_tile(blockIdx.x, gridDim.x);
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -325,21 +394,37 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   const int gy = y0 + oy, gx = x0 + ox;
   const bool out_col = gy < n1 && gx < n2;   // == cin[0]
 
+  // per-thread entries of the window-statistics pass (tile + r halo): LDS
+  // offset, in-plane window count (0 off the grid) and whether the entry is
+  // a tile voxel whose cc enters the loss; fixed across planes
+  constexpr int CPT2 = (E2 + NT - 1) / NT;
+  int e2off[CPT2];
+  float e2cnt[CPT2];
+  bool e2own[CPT2];
+#pragma unroll
+  for (int k = 0; k < CPT2; ++k) {
+    const int c = tid + k * NT;
+    const int yo = c / E2X, xo = c - yo * E2X;
+    const int yy = y0 - R + yo, xx = x0 - R + xo;
+    e2off[k] = yo * E2X + xo;
+    const bool ok = c < E2 && yy >= 0 && yy < n1 && xx >= 0 && xx < n2;
+    e2cnt[k] = ok ? clipped_count(yy, n1, R) * clipped_count(xx, n2, R) : 0.0f;
+    e2own[k] = ok && yo >= R && yo < R + TY && xo >= R && xo < R + TX;
+  }
+
   float ringI[CPT1][W], ringJ[CPT1][W];
-  float ringG0[W], ringG1[W], ringG2[W];   // grad_p I_m of the own column
   float ringA[W], ringB[W], ringC[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) {
 #pragma unroll
     for (int k = 0; k < CPT1; ++k) { ringI[k][j] = 0.0f; ringJ[k][j] = 0.0f; }
     ringA[j] = ringB[j] = ringC[j] = 0.0f;
-    ringG0[j] = ringG1[j] = ringG2[j] = 0.0f;
   }
 
-  const float bc1 = A.ctl->bc1, bc2 = A.ctl->bc2;
+  const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
   if (A.mode == 0 && blockIdx.x == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
-  double lacc = 0.0;
+  float lacc = 0.0f;   // this thread's cc sum over at most 2 zc columns
 
   const int zs = z0 - 2 * R, ze = z1 + 2 * R;
 
@@ -349,6 +434,24 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   float curI[CPT1], curJ[CPT1], curG0 = 0.f, curG1 = 0.f, curG2 = 0.f;
   float nxI[CPT1];
   bool gv[CPT1];
+  auto store_g = [&](int z) {
+    if constexpr (GLDS) {
+      float* gs = gring + (((z % GS) + GS) % GS) * 3 * NT + tid;
+      gs[0] = curG0;
+      gs[NT] = curG1;
+      gs[2 * NT] = curG2;
+    } else {
+#pragma unroll
+      for (int j = 0; j < GS - 1; ++j) {
+        greg[0][j] = greg[0][j + 1];
+        greg[1][j] = greg[1][j + 1];
+        greg[2][j] = greg[2][j + 1];
+      }
+      greg[0][GS - 1] = curG0;
+      greg[1][GS - 1] = curG1;
+      greg[2][GS - 1] = curG2;
+    }
+  };
 
   auto load_raw = [&](int z, int k) {
     if (z >= 0 && z < n0 && cin[k]) {
@@ -362,7 +465,7 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
   auto issue_gather = [&](int z, int k) {
     gv[k] = z >= 0 && z < n0 && cin[k];
     if (gv[k]) {
-      const Corners c = corners_at(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
+      const Cell8 c = cell8_at(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
       gather_issue(A.moving, c, gq[k]);
       nxI[k] = nf[k] - si;
     }
@@ -404,15 +507,7 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
       ringI[k][W - 1] = curI[k];
       ringJ[k][W - 1] = curJ[k];
     }
-#pragma unroll
-    for (int j = 0; j < W - 1; ++j) {
-      ringG0[j] = ringG0[j + 1];
-      ringG1[j] = ringG1[j + 1];
-      ringG2[j] = ringG2[j + 1];
-    }
-    ringG0[W - 1] = curG0;
-    ringG1[W - 1] = curG1;
-    ringG2[W - 1] = curG2;
+    if (R == 0) store_g(zin);
     // next plane: gathers in flight during this plane's passes (PIPE), or
     // issued after them (fewer live registers)
     if (PIPE) {
@@ -469,9 +564,11 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
       const bool z1ok = zc1 >= 0 && zc1 < n0;
       const float cz = clipped_count(zc1, n0, R);
       const bool z1out = zc1 >= z0 && zc1 < z1;
-      for (int c = tid; c < E2; c += NT) {
-        const int yo = c / E2X, xo = c - yo * E2X;
-        const float* src = bufx + yo * E2X + xo;
+#pragma unroll
+      for (int k2 = 0; k2 < CPT2; ++k2) {
+        const int c = tid + k2 * NT;
+        if (c >= E2) break;
+        const float* src = bufx + e2off[k2];
         float SI = 0.f, SJ = 0.f, SII = 0.f, SJJ = 0.f, SIJ = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -481,25 +578,24 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
           SJJ += src[3 * XS1 + k * E2X];
           SIJ += src[4 * XS1 + k * E2X];
         }
-        const int yy = y0 - R + yo, xx = x0 - R + xo;
         float ca = 0.f, cb = 0.f, cc_ = 0.f;
         // A one-voxel window has zero variance and zero covariance exactly, so
         // its correlation and every coefficient are 0 (W == 1 skips the
         // arithmetic that would leave rounding residue).
-        if (W > 1 && z1ok && yy >= 0 && yy < n1 && xx >= 0 && xx < n2) {
-          const float cnt = cz * clipped_count(yy, n1, R) * clipped_count(xx, n2, R);
-          const float muI = SI / cnt, muJ = SJ / cnt;
+        if (W > 1 && z1ok && e2cnt[k2] > 0.0f) {
+          const float icnt = __builtin_amdgcn_rcpf(cz * e2cnt[k2]);
+          const float muI = SI * icnt, muJ = SJ * icnt;
           const float cross = SIJ - muI * SJ;
           const float vI = SII - muI * SI;
           const float vJ = SJJ - muJ * SJ;
           const float D = vI * vJ + A.eps_cc;
           if (D != 0.0f) {
-            const float invD = 1.0f / D;
+            const float invD = __builtin_amdgcn_rcpf(D);
             const float cc = cross * cross * invD;
             ca = 2.0f * cross * invD;
             cb = -2.0f * cc * vI * invD;
             cc_ = ca * muI + cb * muJ;
-            if (z1out && yo >= R && yo < R + TY && xo >= R && xo < R + TX) lacc += (double)cc;
+            if (z1out && e2own[k2]) lacc += cc;
           }
         }
         buf[c] = ca;
@@ -560,7 +656,17 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
         }
         // oldest ring entries of the own column hold plane zc2
         const float dl = -A.inv_n * (ringI[0][0] * SA + ringJ[0][0] * SB - SC);
-        const float g[3] = {dl * ringG0[0], dl * ringG1[0], dl * ringG2[0]};
+        float g[3];
+        if constexpr (GLDS) {
+          const float* gs = gring + (((zc2 % GS) + GS) % GS) * 3 * NT + tid;
+          g[0] = dl * gs[0];
+          g[1] = dl * gs[NT];
+          g[2] = dl * gs[2 * NT];
+        } else {
+          g[0] = dl * greg[0][0];
+          g[1] = dl * greg[1][0];
+          g[2] = dl * greg[2][0];
+        }
         if (A.mode == 0) {
           const float b1 = A.beta1, b2 = A.beta2;
 #pragma unroll
@@ -570,7 +676,7 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
             const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
             A.m[iq] = mm;
             A.v[iq] = vv;
-            A.out[iq] = (mm / bc1) / (sqrtf(vv / bc2) + A.adam_eps);
+            A.out[iq] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps);
           }
           // Adam moments of the next output plane
           mv_ready = zc2 + 1 < z1;
@@ -587,6 +693,7 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
         }
       }
     }
+    if (R > 0) store_g(zin);
     if (!PIPE) {
 #pragma unroll
       for (int k = 0; k < CPT1; ++k) {
@@ -597,8 +704,20 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
 #pragma unroll
     for (int k = 0; k < CPT1; ++k) finish_gather(k);
   }
-  const double tot = block_sum<NT>(lacc, red);
+  const double tot = block_sum<NT>((double)lacc, red);
   if (tid == 0) A.partials[blockIdx.x] = tot;
+}
+
+template <int W, int TY, int TX, bool PIPE>
+__global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
+  grad_body<W, TY, TX, PIPE>(A);
+}
+
+// The same kernel compiled for two workgroups per CU (at most 128 VGPRs);
+// used where that fits without spilling.
+template <int W, int TY, int TX, bool PIPE>
+__global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4))) k_grad_o4(const GradArgs A) {
+  grad_body<W, TY, TX, PIPE>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -615,14 +734,17 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   constexpr int EY = TY + 2 * R, EX = TX + 2 * R, E = EY * EX;
   constexpr int XS = EY * TX;
   constexpr int CPT = (E + NT - 1) / NT;
+  constexpr int DY = TY + 2, DX = TX + 2, DE = DY * DX;  // staged d planes (EPI_COMPOSE_LDS)
+  constexpr int CPTD = (DE + NT - 1) / NT;
   extern __shared__ float lds[];
   float* buf = lds;           // [3][E]
   float* bufx = lds + 3 * E;  // [3][XS]
+  float* dring = lds + 3 * E + 3 * XS;  // [3 planes][3][DE] (EPI_COMPOSE_LDS)
   __shared__ double red[NT / 64];
   __shared__ int is_last;
 
   const int tid = threadIdx.x;
-  int b = blockIdx.x;
+  int b = xcd_tile(blockIdx.x, gridDim.x);
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -656,7 +778,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   for (int k = 0; k < L; ++k) ring[0][k] = ring[1][k] = ring[2][k] = 0.0f;
 
   float scale = 0.0f;
-  if (EPI == EPI_COMPOSE) {
+  if (EPI == EPI_COMPOSE || EPI == EPI_COMPOSE_LDS) {
     const float M = __uint_as_float(A.ctl->mbits);
     scale = M > 0.0f ? -A.eta / (2.0f * M) : 0.0f;
   }
@@ -676,6 +798,43 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
       }
     }
   };
+
+  // d planes for the LDS composition: plane p lives in slot p mod 3 and
+  // covers the tile plus one voxel on each side, zero off the grid (the
+  // zero extension of the trilinear sample)
+  float pd[CPTD][3];
+  auto load_dplane = [&](int pz) {
+#pragma unroll
+    for (int k = 0; k < CPTD; ++k) {
+      const int c = tid + k * NT;
+      const int yy = y0 - 1 + c / DX, xx = x0 - 1 + c % DX;
+      const bool ok = c < DE && pz >= 0 && pz < n0 && yy >= 0 && yy < n1 && xx >= 0 && xx < n2;
+      const int idx = ok ? (pz * n1 + yy) * n2 + xx : 0;
+      pd[k][0] = ok ? A.d[idx] : 0.0f;
+      pd[k][1] = ok ? A.d[N + idx] : 0.0f;
+      pd[k][2] = ok ? A.d[2 * N + idx] : 0.0f;
+    }
+  };
+  auto store_dplane = [&](int pz) {
+    const int slot = ((pz % 3) + 3) % 3;
+#pragma unroll
+    for (int k = 0; k < CPTD; ++k) {
+      const int c = tid + k * NT;
+      if (c < DE) {
+        dring[(slot * 3 + 0) * DE + c] = pd[k][0];
+        dring[(slot * 3 + 1) * DE + c] = pd[k][1];
+        dring[(slot * 3 + 2) * DE + c] = pd[k][2];
+      }
+    }
+  };
+  if (EPI == EPI_COMPOSE_LDS) {
+    const int p0 = z0 - 2 * R + 1;   // plane stored by the first step (zin - R + 1)
+    load_dplane(p0 - 2);
+    store_dplane(p0 - 2);
+    load_dplane(p0 - 1);
+    store_dplane(p0 - 1);
+    load_dplane(p0);
+  }
 
   // composition gathers in flight (EPI_COMPOSE)
   Gather cg[3];
@@ -703,6 +862,12 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
     }
     if (zin + 1 < z1 + R) load_plane(zin + 1);
     __syncthreads();
+    if (EPI == EPI_COMPOSE_LDS) {
+      // plane zo + 1 joins the ring (slot of zo - 2, last read before the
+      // barrier above); the next plane's loads go out now
+      store_dplane(zin - R + 1);
+      if (zin + 1 < z1 + R) load_dplane(zin - R + 2);
+    }
     for (int c = tid; c < XS; c += NT) {
       const int yy = c / TX, xo = c - yy * TX;
       const float* src = buf + yy * EX + xo;
@@ -754,11 +919,39 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
         A.out[2 * N + idx] = v2;
       } else if (EPI == EPI_MAXNORM) {
         mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
+      } else if (EPI == EPI_COMPOSE_LDS) {
+        // d' = u + d(x + u) from the staged planes zo - 1 .. zo + 1; the
+        // cell offset floor(u) is -1 or 0 for |u| <= 1 (u = 1 exactly uses
+        // offset 0 with fraction 1, which selects the same corner value)
+        const float u0 = scale * v0, u1 = scale * v1, u2 = scale * v2;
+        const float f0 = fminf(fmaxf(floorf(u0), -1.0f), 0.0f);
+        const float f1 = fminf(fmaxf(floorf(u1), -1.0f), 0.0f);
+        const float f2 = fminf(fmaxf(floorf(u2), -1.0f), 0.0f);
+        const float t0 = u0 - f0, t1 = u1 - f1, t2 = u2 - f2;
+        const int sA = (((zo + (int)f0) % 3) + 3) % 3;
+        const int sB = (sA + 1) % 3;
+        const int cb = (oy + 1 + (int)f1) * DX + (ox + 1 + (int)f2);
+        float res[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float* pa = dring + (sA * 3 + q) * DE + cb;
+          const float* pb = dring + (sB * 3 + q) * DE + cb;
+          const float e00 = pa[0] + t2 * (pa[1] - pa[0]);
+          const float e01 = pa[DX] + t2 * (pa[DX + 1] - pa[DX]);
+          const float e10 = pb[0] + t2 * (pb[1] - pb[0]);
+          const float e11 = pb[DX] + t2 * (pb[DX + 1] - pb[DX]);
+          const float g0 = e00 + t1 * (e01 - e00);
+          const float g1 = e10 + t1 * (e11 - e10);
+          res[q] = g0 + t0 * (g1 - g0);
+        }
+        A.out[idx] = u0 + res[0];
+        A.out[N + idx] = u1 + res[1];
+        A.out[2 * N + idx] = u2 + res[2];
       } else {  // EPI_COMPOSE: d' = u + d(x + u); finished next plane step
         cu[0] = scale * v0;
         cu[1] = scale * v1;
         cu[2] = scale * v2;
-        const Corners c = corners_at(n0, n1, n2, zo, gy, gx, cu[0], cu[1], cu[2]);
+        const Cell8 c = cell8_at(n0, n1, n2, zo, gy, gx, cu[0], cu[1], cu[2]);
         gather_issue(A.d, c, cg[0]);
         gather_issue(A.d + N, c, cg[1]);
         gather_issue(A.d + 2 * N, c, cg[2]);
@@ -854,8 +1047,10 @@ __global__ void k_warp(const float* __restrict__ img, const float* __restrict__ 
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int x = i % n2, y = (i / n2) % n1, z = i / (n1 * n2);
-  const Corners c = corners_at(n0, n1, n2, z, y, x, d[i], d[N + i], d[2 * N + i]);
-  out[i] = tri(img, c);
+  const Cell8 c = cell8_at(n0, n1, n2, z, y, x, d[i], d[N + i], d[2 * N + i]);
+  Gather g;
+  gather_issue(img, c, g);
+  out[i] = gather_value(g);
 }
 
 __global__ void k_soa_to_aos(const float* __restrict__ in, float* __restrict__ out, int64_t n) {
@@ -911,21 +1106,32 @@ __global__ void k_sum_final(const double* __restrict__ part, int np, double* __r
 template <int W, int TY, int TX>
 constexpr size_t grad_lds() {
   constexpr int R = W / 2;
-  return sizeof(float) * (5 * (TY + 4 * R) * (TX + 4 * R) + 5 * (TY + 4 * R) * (TX + 2 * R));
+  constexpr int GS = (R == 0) ? 1 : 2 * R;
+  constexpr size_t base = sizeof(float) * (5 * (TY + 4 * R) * (TX + 4 * R) + 5 * (TY + 4 * R) * (TX + 2 * R));
+  constexpr size_t ring = sizeof(float) * 3 * GS * TY * TX;
+  return base + ring <= 65536 ? base + ring : base;
 }
 
 template <int R, int TY, int TX>
-constexpr size_t gauss_lds() {
-  return sizeof(float) * (3 * (TY + 2 * R) * (TX + 2 * R) + 3 * (TY + 2 * R) * TX);
+constexpr size_t gauss_lds(bool staged_d) {
+  return sizeof(float) * (3 * (TY + 2 * R) * (TX + 2 * R) + 3 * (TY + 2 * R) * TX +
+                          (staged_d ? 9 * (TY + 2) * (TX + 2) : 0));
 }
 
 template <int W, int TY, int TX>
 hipError_t grad_launch_t(const GradArgs& a, const Tiling& t, hipStream_t s) {
   constexpr size_t sh = grad_lds<W, TY, TX>();
-  if (t.variant == 2)
-    k_grad<W, TY, TX, false><<<dim3(t.blocks()), dim3(TY * TX), sh, s>>>(a);
-  else
-    k_grad<W, TY, TX, true><<<dim3(t.blocks()), dim3(TY * TX), sh, s>>>(a);
+  static_assert(sh <= 65536, "gradient kernel LDS exceeds 64 KiB");
+  // two workgroups per CU where 128 VGPRs hold the kernel without spills
+  constexpr bool occ2 = (W <= 5) && TY == 16 && TX == 32;
+  const dim3 g(t.blocks()), blk(TY * TX);
+  if constexpr (occ2) {
+    if (t.variant == 2) k_grad_o4<W, TY, TX, false><<<g, blk, sh, s>>>(a);
+    else k_grad_o4<W, TY, TX, true><<<g, blk, sh, s>>>(a);
+  } else {
+    if (t.variant == 2) k_grad<W, TY, TX, false><<<g, blk, sh, s>>>(a);
+    else k_grad<W, TY, TX, true><<<g, blk, sh, s>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -944,12 +1150,13 @@ hipError_t grad_launch_tile(const GradArgs& a, int window, const Tiling& t, hipS
 template <int R, int TY, int TX>
 hipError_t gauss_launch_r(const GaussArgs& a, int epi, const Tiling& t, hipStream_t s) {
   const dim3 g(t.blocks()), blk(TY * TX);
-  const size_t sh = gauss_lds<R, TY, TX>();
+  const size_t sh = gauss_lds<R, TY, TX>(epi == EPI_COMPOSE_LDS);
   switch (epi) {
     case EPI_STORE: k_gauss<R, TY, TX, EPI_STORE><<<g, blk, sh, s>>>(a); break;
     case EPI_MAXNORM: k_gauss<R, TY, TX, EPI_MAXNORM><<<g, blk, sh, s>>>(a); break;
     case EPI_COMPOSE: k_gauss<R, TY, TX, EPI_COMPOSE><<<g, blk, sh, s>>>(a); break;
     case EPI_STORE_FINAL: k_gauss<R, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(a); break;
+    case EPI_COMPOSE_LDS: k_gauss<R, TY, TX, EPI_COMPOSE_LDS><<<g, blk, sh, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -971,26 +1178,27 @@ hipError_t gauss_launch_tile(const GaussArgs& a, int radius, int epi, const Tili
 
 }  // namespace
 
-bool grad_tile_supported(int ty, int tx) {
-  return (ty == 16 && tx == 32) || (ty == 8 && tx == 32) || (ty == 8 && tx == 64);
-}
+bool grad_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
 bool gauss_tile_supported(int ty, int tx) {
   return (ty == 16 && tx == 32) || (ty == 8 && tx == 32) || (ty == 8 && tx == 64);
 }
 
 size_t grad_lds_bytes(int window, int ty, int tx) {
   const int R = window / 2;
-  return sizeof(float) * (size_t)(5 * (ty + 4 * R) * (tx + 4 * R) + 5 * (ty + 4 * R) * (tx + 2 * R));
+  const int GS = (R == 0) ? 1 : 2 * R;
+  const size_t base = sizeof(float) * (size_t)(5 * (ty + 4 * R) * (tx + 4 * R) + 5 * (ty + 4 * R) * (tx + 2 * R));
+  const size_t ring = sizeof(float) * (size_t)(3 * GS * ty * tx);
+  return base + ring <= 65536 ? base + ring : base;
 }
 
 size_t gauss_lds_bytes(int radius, int ty, int tx) {
-  return sizeof(float) * (size_t)(3 * (ty + 2 * radius) * (tx + 2 * radius) + 3 * (ty + 2 * radius) * tx);
+  return sizeof(float) * (size_t)(3 * (ty + 2 * radius) * (tx + 2 * radius) + 3 * (ty + 2 * radius) * tx +
+                                  9 * (ty + 2) * (tx + 2));
 }
 
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
   if (t.ty == 16 && t.tx == 32) return grad_launch_tile<16, 32>(a, window, t, s);
   if (t.ty == 8 && t.tx == 32) return grad_launch_tile<8, 32>(a, window, t, s);
-  if (t.ty == 8 && t.tx == 64) return grad_launch_tile<8, 64>(a, window, t, s);
   return hipErrorInvalidValue;
 }
 

@@ -77,7 +77,10 @@ Tiling choose_tiling(const fa_shape& s, int halo, const Tuning& tu = Tuning()) {
   t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
   t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
   const int plane_tiles = t.tiles_y * t.tiles_x;
-  const int target = (t.ty == 16) ? 640 : 1024;       // workgroups in flight
+  // About 420 workgroups (1.6 per CU) balances the warm-up planes every
+  // chunk repeats against filling the chip; small levels use the shortest
+  // chunks (4 planes, or the halo) for parallelism.
+  const int target = 420;
   int chunks = std::max(1, (target + plane_tiles - 1) / plane_tiles);
   int zc = (s.n0 + chunks - 1) / chunks;
   zc = std::max(zc, std::max(4, halo));
@@ -199,8 +202,9 @@ fa_status check_params(const fa_params* p) {
 
 fa_status check_shape(const fa_shape& s) {
   if (s.n0 < 2 || s.n1 < 2 || s.n2 < 2) return fail(FA_ESHAPE, "every dimension must be >= 2");
-  if (3 * (double)s.n0 * s.n1 * s.n2 >= 2147483647.0)
-    return fail(FA_ESHAPE, "volume too large: 3*n0*n1*n2 must be < 2^31");
+  // gathers address one volume with 32-bit signed byte offsets
+  if ((double)s.n0 * s.n1 * s.n2 > 536870911.0)
+    return fail(FA_ESHAPE, "volume too large: n0*n1*n2 must be < 2^29");
   return FA_OK;
 }
 
@@ -305,7 +309,10 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   fa::GaussArgs g2 = g1;  // d' = u + d(x + u)
   g2.out = P->tmp;
   g2.d = P->d;
-  FA_HIP(fa::launch_gauss(g2, P->rg, fa::EPI_COMPOSE, L.tsg, P->stream));
+  // |u| <= eta / 2: with eta <= 2 the sample stays within one voxel, and d
+  // is staged in LDS instead of gathered
+  const int epi_c = P->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE;
+  FA_HIP(fa::launch_gauss(g2, P->rg, epi_c, L.tsg, P->stream));
   if (P->profiling) FA_HIP(hipEventRecord(pe.e[3], P->stream));
 
   fa::GaussArgs g3 = gs;  // d = G * d'; record loss, advance t

@@ -122,6 +122,26 @@ def test_one_iteration_from_injected_state(shape):
     pr.close()
 
 
+@pytest.mark.parametrize("eta,sigma_grad,sigma_warp", [(2.0, 0.3, 0.0), (3.0, 0.5, 1.0), (0.25, 0.0, 0.4),
+                                                      (1.0, 2.0, 2.0)])
+def test_one_iteration_step_variants(eta, sigma_grad, sigma_warp):
+    """Both composition paths (staged in LDS for eta <= 2, gathered beyond)
+    and Gaussian radii 0..6, from an injected state."""
+    shape = (19, 33, 41)
+    fixed, moving, d = make_problem(shape, seed=33)
+    P = O.Params(eta=eta, sigma_grad=sigma_grad, sigma_warp=sigma_warp, window=3)
+    pr = new_pair(fixed, moving, eta=eta, sigma_grad=sigma_grad, sigma_warp=sigma_warp, window=3)
+    pr.set_schedule([1.0], [1])
+    pr.set_state(dev(d), None, None, 0)
+    pr.step(1)
+    d1 = host(pr.state()[0])
+    z = np.zeros((3,) + shape)
+    ref_d, _, _, _, ex = O.iterate(fixed, moving, d.astype(np.float64), z, z, 1, P)
+    assert rel_l2(d1 - d, ref_d - d) <= TOL_G
+    assert abs(pr.step_norm() - ex["M"]) <= TOL_G * ex["M"]
+    pr.close()
+
+
 def test_first_iteration_moves_at_most_eta_over_two():
     fixed, moving, _ = make_problem((21, 37, 45), seed=41)
     pr = new_pair(fixed, moving, eta=0.5, sigma_grad=1.0, sigma_warp=0.0)
