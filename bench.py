@@ -30,20 +30,25 @@ if ROOT not in sys.path:
 METRIC = "voxel-iters/sec @160×192×224 fused vs plain per-op GPU, same accuracy"
 HBM_PEAK_GBS = 8000.0
 GRAD_BYTES_PER_VOXEL = 80   # reads I_f, I_m, d(3), m(3), v(3); writes m(3), v(3), a(3); fp32
-KERNEL_SRC = os.path.join(ROOT, "paper_2404_01249_amd", "csrc", "fa_kernels.hip")
+# the counters depend on the kernels and on the launch shapes the runtime picks
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2404_01249_amd", "csrc", f)
+                   for f in ("fa_kernels.hip", "fa_runtime.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_tissue160_traffic.json")
 
 
 def kernel_source_hash():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the gradient kernel at the finest level, from
     the committed rocprofv3 counter summary, if it was taken on the current
-    kernel source (else None)."""
+    kernel and runtime sources (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)

@@ -63,12 +63,16 @@ struct Tuning {
   int ty = 0, tx = 0, zc = 0, variant = 0;
 };
 
-// In-plane tile and n0 chunking of one streaming launch.  halo = planes of
-// look-ahead the kernel needs on each side of its chunk.
+// In-plane tile and n0 chunking of one streaming launch.  16x32 tiles (8x32
+// when n1 is smaller); the chunk is the longest that keeps the launch within
+// about 512 workgroups (two per CU on 256 CUs), so that every workgroup is
+// resident at once, and at least 2 planes.  (Measured on the 160x192x224
+// pyramid: each level's best chunk length in a sweep of 2..32 planes.)
 Tiling choose_tiling(const fa_shape& s, int halo, const Tuning& tu = Tuning()) {
+  (void)halo;
   Tiling t;
   t.tx = 32;
-  t.ty = (s.n1 * s.n2 >= 128 * 128) ? 16 : 8;
+  t.ty = s.n1 >= 16 ? 16 : 8;
   if (tu.ty > 0 && tu.tx > 0) {
     t.ty = tu.ty;
     t.tx = tu.tx;
@@ -77,13 +81,9 @@ Tiling choose_tiling(const fa_shape& s, int halo, const Tuning& tu = Tuning()) {
   t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
   t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
   const int plane_tiles = t.tiles_y * t.tiles_x;
-  // About 420 workgroups (1.6 per CU) balances the warm-up planes every
-  // chunk repeats against filling the chip; small levels use the shortest
-  // chunks (4 planes, or the halo) for parallelism.
-  const int target = 420;
-  int chunks = std::max(1, (target + plane_tiles - 1) / plane_tiles);
-  int zc = (s.n0 + chunks - 1) / chunks;
-  zc = std::max(zc, std::max(4, halo));
+  constexpr int kSlots = 512;
+  int zc = (int)(((int64_t)s.n0 * plane_tiles + kSlots - 1) / kSlots);
+  zc = std::max(zc, 2);
   if (tu.zc > 0) zc = tu.zc;
   zc = std::min(zc, s.n0);
   t.zc = zc;
