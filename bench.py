@@ -14,6 +14,9 @@ Prints one JSON line.  Besides the headline value it reports
   during the timed steps, against the 8 TB/s HBM peak;
 * ``plain_torch``: the same algorithm written with stock PyTorch operators
   (grid_sample, conv3d, autograd, elementwise Adam) on the same GPU;
+* ``accuracy``: Dice of the transferred tissue labels and the fraction of
+  singular voxels for the fused result and the plain PyTorch result (the
+  "same accuracy" condition of the comparison);
 * ``cpu_baseline``: the FP64 NumPy oracle timed on the host, on a bounded
   sample of the same workload.
 """
@@ -97,8 +100,9 @@ def run_fused(p, steps, warmup, params):
         prof[lvl] = [fa.fa_pair_get_profile(pr.handle, lvl, k) for k in range(4)]
     fa.fa_pair_profile(pr.handle, False)
     loss = pr.loss_history()
+    field = pr.field()
     pr.close()
-    return ms, wall / steps, prof, loss
+    return ms, wall / steps, prof, loss, field
 
 
 def run_plain(p, steps, warmup, params):
@@ -116,7 +120,22 @@ def run_plain(p, steps, warmup, params):
         d, losses = bench_plain.register(fixed, moving, p.scales, p.iters, **params)
     end.record()
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps, losses
+    return start.elapsed_time(end) / steps, losses, d.contiguous()
+
+
+def accuracy(p, d):
+    """Dice of the moving labels transferred by d against the fixed labels
+    (mean over the 4 tissue classes) and the singular-voxel fraction,
+    computed by the library's evaluation kernels."""
+    import torch
+
+    from paper_2404_01249_amd import evaluate
+    if p.fixed_labels is None:
+        return {}
+    fl = torch.from_numpy(p.fixed_labels).cuda()
+    ml = torch.from_numpy(p.moving_labels).cuda()
+    return {"dice": evaluate.dice(evaluate.warp_labels(ml, d), fl, 4),
+            "singular_fraction": evaluate.singular_fraction(d)}
 
 
 def cpu_baseline(p, params, budget_s=20.0):
@@ -185,7 +204,7 @@ def main():
     lv = level_voxels(p.fixed.shape, p.scales, p.iters)
     vox_iters = sum(n * t for n, t in lv)
 
-    ms, wall_ms, prof, loss = run_fused(p, args.steps, args.warmup, params)
+    ms, wall_ms, prof, loss, field = run_fused(p, args.steps, args.warmup, params)
     value = vox_iters / (ms / 1e3)
 
     # dominant kernel: the fused gradient kernel at the finest level
@@ -221,11 +240,20 @@ def main():
         "wall_ms_per_step": wall_ms * 1e3,
         "final_loss": float(loss[-1]) if len(loss) else None,
     }
+    acc = accuracy(p, field)
+    if acc:
+        import torch
+        zero = torch.zeros_like(field)
+        out["accuracy"] = {"fused": acc, "identity_dice": accuracy(p, zero)["dice"]}
     if not args.no_plain:
         try:
-            pms, plosses = run_plain(p, args.plain_steps, 0, params)
+            pms, plosses, pfield = run_plain(p, args.plain_steps, 0, params)
             out["plain_torch"] = {"value": vox_iters / (pms / 1e3), "ms_per_step": pms,
                                   "speedup_fused": pms / ms, "final_loss": float(plosses[-1])}
+            if acc:
+                pacc = accuracy(p, pfield)
+                out["accuracy"]["plain_torch"] = pacc
+                out["accuracy"]["dice_difference"] = acc["dice"] - pacc["dice"]
         except Exception as e:  # the comparison must not hide the headline line
             out["plain_torch"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:

@@ -52,20 +52,22 @@ fa_status fa_pair_get_level_image(fa_pair pair, int level, int which, float* dev
 
 /* Kernel timing.  While enabled (enable = 1), every iteration records HIP
  * events on the pair's stream around each of its kernels; kind 0 = gradient
- * (warp, LNCC, adjoint, Adam), 1 = smoothed-step norm, 2 = composition,
- * 3 = warp smoothing.  fa_pair_get_profile synchronises the stream and
+ * (warp, LNCC, adjoint, Adam), 1 = smoothed direction and its maximum norm,
+ * 2 = composition, 3 = warp smoothing.  fa_pair_get_profile synchronises the stream and
  * returns, for level `level` and kernel `kind`, the summed duration in
  * milliseconds and the number of launches recorded since profiling was last
  * enabled.  Enabling clears the totals. */
 fa_status fa_pair_profile(fa_pair pair, int enable);
 fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_ms, int* launches);
 
-/* Launch-shape override for tuning.  kind 0 = gradient kernel, 1 = the two
- * sigma_grad smoothing kernels, 2 = the sigma_warp smoothing kernel.  ty x tx
+/* Launch-shape override for tuning.  kind 0 = gradient kernel, 1 = the
+ * sigma_grad smoothing kernel (smoothed direction and its maximum norm),
+ * 2 = the sigma_warp smoothing kernel, 3 = the composition kernel.  ty x tx
  * is the in-plane tile (n1 x n2): 16x32 or 8x32 for every kind, 8x64 also for
- * kinds 1 and 2, or 0x0 for the automatic choice; zc is the number of n0 planes per workgroup (0 =
- * automatic); variant selects the gradient kernel's schedule (0 automatic,
- * 1 next-plane gathers overlapped with the LDS passes, 2 issued after them).
+ * kinds 1 to 3, or 0x0 for the automatic choice; zc is the number of n0 planes
+ * per workgroup (0 = automatic); variant selects the gradient kernel's
+ * schedule (0 automatic, 1 next-plane gathers overlapped with the LDS passes,
+ * 2 issued after them).
  * Takes effect at the next fa_pair_set_schedule.  Results do not depend on
  * the launch shape beyond floating-point summation order. */
 fa_status fa_pair_set_tuning(fa_pair pair, int kind, int ty, int tx, int zc, int variant);

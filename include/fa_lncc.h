@@ -1,0 +1,58 @@
+/*
+ * fa_lncc.h -- the fused LNCC cost and its Gateaux gradient as a stateless
+ * call, for use as a differentiable loss outside the registration driver.
+ *
+ * For a fixed image I, a moving image I_m and a displacement d (voxel units),
+ * the call evaluates, in one streaming pass over the volume,
+ *
+ *   J(x)  = I_m(x + d(x))                    trilinear, zero outside the grid
+ *   L     = -(1/N) sum_x cc(x)               cc = cross^2 / (v_I v_J + eps)
+ *   dL/dd = dL/dJ (x) * grad I_m (x + d(x))  (Section 4.4.2: the gradient of
+ *                                             the cost with respect to the
+ *                                             warp, without the Jacobian term)
+ *
+ * over windows of w^3 voxels clipped to the grid and normalised by their
+ * voxel count.  This is the computation of one iteration of Algorithm 1 up to
+ * the optimiser, with the same kernels and the same readings as fa.h
+ * (cross, v_I, v_J are sum-form window (co)variances; eps is added to their
+ * product; the derivative at an integer sample position is the one-sided
+ * derivative of the cell holding it).
+ *
+ * Conventions as in fa.h: float32 volumes in C order [n0][n1][n2] in device
+ * memory, displacement SoA [3][n0][n1][n2]; work is enqueued on the stream
+ * given at creation; every call returns an fa_status and never aborts.
+ */
+#ifndef FA_LNCC_H_
+#define FA_LNCC_H_
+
+#include "fa.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fa_lncc_s* fa_lncc;   /* opaque; owns its reduction buffers */
+
+/* Create an evaluator for volumes of `shape` (every dimension >= 2,
+ * n0*n1*n2 < 2^29), window w (odd, 1..9) and eps >= 0.  Allocates a few KB of
+ * device memory; work is enqueued on `hip_stream` (NULL = null stream). */
+fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_stream, fa_lncc* out);
+
+/* Evaluate at (fixed, moving, d), all device pointers of the evaluator's shape.
+ *   loss_dev:  device float receiving L (may be NULL).
+ *   grad_dev:  device [3][n0][n1][n2] receiving dL/dd, or NULL for the loss only.
+ *   grad_scale_dev: device float multiplying the gradient (the upstream
+ *              derivative of a chain rule), or NULL for 1.
+ * At least one of loss_dev and grad_dev must be non-NULL.  Enqueued; calls on
+ * one evaluator must not overlap (they share its reduction buffers). */
+fa_status fa_lncc_eval(fa_lncc h, const float* fixed, const float* moving, const float* d,
+                       float* loss_dev, float* grad_dev, const float* grad_scale_dev);
+
+/* Destroy (synchronises the stream).  NULL is a no-op. */
+void fa_lncc_destroy(fa_lncc h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FA_LNCC_H_ */

@@ -7,10 +7,11 @@ only provides device memory and streams.
 """
 from __future__ import annotations
 
-from . import fa
+from . import evaluate, fa
 from .fa import FAError
+from .lncc import LNCC
 
-__all__ = ["Pair", "FAError", "fa"]
+__all__ = ["Pair", "FAError", "fa", "LNCC", "evaluate"]
 
 
 class Pair:
@@ -39,7 +40,6 @@ class Pair:
     def set_schedule(self, scales, iters):
         fa.fa_pair_set_schedule(self.handle, scales, iters)
         self.total_iters = int(sum(iters))
-        self._keep = None if self._keep is None else self._keep
 
     def step(self, n):
         return fa.fa_pair_step(self.handle, n)

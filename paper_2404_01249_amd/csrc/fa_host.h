@@ -1,0 +1,47 @@
+// Host-side helpers shared by the sources of the C ABI: error reporting,
+// status macros, shape checks and the launch-shape heuristic of the
+// streaming kernels.  Not part of the public interface.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+
+#include "fa.h"
+#include "fa_internal.h"
+
+namespace fa {
+
+// Records msg as the calling thread's last error (returned by fa_last_error)
+// and returns s.
+fa_status fail(fa_status s, const std::string& msg);
+
+// Every dimension >= 2 and n0*n1*n2 < 2^29 (gathers address a volume with
+// 32-bit signed byte offsets).
+fa_status check_shape(const fa_shape& s);
+
+inline int64_t voxels(const fa_shape& s) { return (int64_t)s.n0 * s.n1 * s.n2; }
+
+// Launch-shape override of one streaming kernel kind (0 = auto).
+struct Tuning {
+  int ty = 0, tx = 0, zc = 0, variant = 0;
+};
+
+// In-plane tile and n0 chunking of one streaming launch over a volume of
+// shape s.
+Tiling choose_tiling(const fa_shape& s, const Tuning& tu = Tuning());
+
+}  // namespace fa
+
+#define FA_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fa::fail(FA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define FA_TRY(call)                       \
+  do {                                     \
+    fa_status s_ = (call);                 \
+    if (s_ != FA_OK) return s_;            \
+  } while (0)

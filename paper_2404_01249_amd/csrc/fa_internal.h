@@ -40,6 +40,7 @@ struct GradArgs {
   float* m;              // [3][N] (Adam mode)
   float* v;              // [3][N]
   float* out;            // [3][N]: Adam direction (mode 0) or gradient (mode 1)
+  const float* gscale;   // mode 1: optional device scalar multiplying the gradient
   double* partials;      // per-workgroup sum of cc
   Ctl* ctl;
   int n0, n1, n2;
@@ -47,14 +48,22 @@ struct GradArgs {
   float eps_cc;
   float beta1, beta2, adam_eps;
   float inv_n;
-  int mode;
+  int mode;              // 0: gradient + Adam; 1: gradient only; 2: loss only
 };
 
 // ---- streaming separable Gaussian on a 3-channel field ---------------------
 // EPI_COMPOSE samples d with global gathers (any step length);
 // EPI_COMPOSE_LDS stages three planes of d in LDS and needs |u| <= 1 voxel
 // (eta <= 2, since max |u| = eta / 2).
-enum GaussEpilogue { EPI_STORE = 0, EPI_MAXNORM = 1, EPI_COMPOSE = 2, EPI_STORE_FINAL = 3, EPI_COMPOSE_LDS = 4 };
+// EPI_SMOOTH_MAX stores the smoothed field and takes M = max |s| in one pass.
+enum GaussEpilogue {
+  EPI_STORE = 0,
+  EPI_MAXNORM = 1,
+  EPI_COMPOSE = 2,
+  EPI_STORE_FINAL = 3,
+  EPI_COMPOSE_LDS = 4,
+  EPI_SMOOTH_MAX = 5
+};
 
 struct GaussArgs {
   const float* in;       // [3][N]
@@ -90,6 +99,8 @@ hipError_t launch_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int i
 // Mean of x (n values) into *dst (device float), via `scratch` (kMeanBlocks doubles).
 hipError_t launch_mean(const float* x, int64_t n, double* scratch, float* dst, hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int n, double* dst, hipStream_t s);
+// (float)(sum of n partials / denom) into *dst (device float).
+hipError_t launch_partials_ratio(const double* partials, int n, double denom, float* dst, hipStream_t s);
 constexpr int kMeanBlocks = 256;
 
 bool grad_tile_supported(int ty, int tx);

@@ -6,9 +6,9 @@
 //            Gateaux gradient g = dL/dJ * grad_p I_m (Jacobian-free Eulerian
 //            descent, Section 4.4.2) and the Adam update (Section 4.4) ->
 //            m, v, direction a; per-workgroup loss partials.
-//   gauss  : s = G_sigma_grad * a, M = max |s|              (EPI_MAXNORM)
-//   gauss  : s again, u = -eta s / (2M) (Appendix E), d' = u + d(x + u)
-//            (the retraction phi o (id + u) of Algorithm 1)  (EPI_COMPOSE)
+//   gauss  : s = G_sigma_grad * a stored, M = max |s|     (EPI_SMOOTH_MAX)
+//   gauss  : single tap: u = -eta s / (2M) (Appendix E), d' = u + d(x + u)
+//            (the retraction phi o (id + u) of Algorithm 1)  (EPI_COMPOSE_LDS)
 //   gauss  : d = G_sigma_warp * d'; the last workgroup records the loss and
 //            advances the Adam step count                   (EPI_STORE_FINAL)
 //
@@ -318,6 +318,10 @@ __device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex)
     ex = H + tid % TX;
     return true;
   }
+  if constexpr (H == 0) {
+    ey = ex = 0;
+    return false;
+  } else {
   const int h = tid + (slot - 1) * NT;
   constexpr int TB = H * EX;       // one horizontal band
   constexpr int LB = TY * H;       // one vertical band
@@ -338,6 +342,7 @@ __device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex)
     return false;
   }
   return true;
+  }
 }
 
 template <int W, int TY, int TX, bool PIPE>
@@ -424,6 +429,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
   const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
   if (A.mode == 0 && blockIdx.x == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
+  const float gsc = (A.mode == 1 && A.gscale) ? *A.gscale : 1.0f;
   float lacc = 0.0f;   // this thread's cc sum over at most 2 zc columns
 
   const int zs = z0 - 2 * R, ze = z1 + 2 * R;
@@ -687,9 +693,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
               pv[q] = A.v[q * N + idx + n1 * n2];
             }
           }
-        } else {
+        } else if (A.mode == 1) {
 #pragma unroll
-          for (int q = 0; q < 3; ++q) A.out[q * N + idx] = g[q];
+          for (int q = 0; q < 3; ++q) A.out[q * N + idx] = g[q] * gsc;
         }
       }
     }
@@ -851,6 +857,20 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
 
   load_plane(z0 - R);
   for (int zin = z0 - R; zin < z1 + R; ++zin) {
+    if constexpr (R == 0) {
+      // a single tap: the thread's own column is the output; no LDS passes
+      ring[0][0] = pre[0][0];
+      ring[1][0] = pre[0][1];
+      ring[2][0] = pre[0][2];
+      if (zin + 1 < z1) load_plane(zin + 1);
+      if (EPI == EPI_COMPOSE_LDS) {
+        __syncthreads();   // the previous step's reads of the d ring are done
+        store_dplane(zin + 1);
+        if (zin + 1 < z1) load_dplane(zin + 2);
+        __syncthreads();
+      }
+      if (EPI == EPI_COMPOSE) finish_compose();
+    } else {
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       if (cuse[k]) {
@@ -903,6 +923,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
       ring[1][L - 1] = s1;
       ring[2][L - 1] = s2;
     }
+    }
     const int zo = zin - R;
     if (zo >= z0 && out_col) {
       float v0 = 0.f, v1 = 0.f, v2 = 0.f;
@@ -918,6 +939,11 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
         A.out[N + idx] = v1;
         A.out[2 * N + idx] = v2;
       } else if (EPI == EPI_MAXNORM) {
+        mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
+      } else if (EPI == EPI_SMOOTH_MAX) {
+        A.out[idx] = v0;
+        A.out[N + idx] = v1;
+        A.out[2 * N + idx] = v2;
         mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
       } else if (EPI == EPI_COMPOSE_LDS) {
         // d' = u + d(x + u) from the staged planes zo - 1 .. zo + 1; the
@@ -961,7 +987,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   }
   if (EPI == EPI_COMPOSE) finish_compose();
 
-  if (EPI == EPI_MAXNORM) {
+  if (EPI == EPI_MAXNORM || EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
   }
@@ -1157,6 +1183,7 @@ hipError_t gauss_launch_r(const GaussArgs& a, int epi, const Tiling& t, hipStrea
     case EPI_COMPOSE: k_gauss<R, TY, TX, EPI_COMPOSE><<<g, blk, sh, s>>>(a); break;
     case EPI_STORE_FINAL: k_gauss<R, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(a); break;
     case EPI_COMPOSE_LDS: k_gauss<R, TY, TX, EPI_COMPOSE_LDS><<<g, blk, sh, s>>>(a); break;
+    case EPI_SMOOTH_MAX: k_gauss<R, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1257,6 +1284,11 @@ hipError_t launch_mean(const float* x, int64_t n, double* scratch, float* dst, h
 
 hipError_t launch_sum_partials(const double* partials, int n, double* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partials, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_partials_ratio(const double* partials, int n, double denom, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(256), 0, s, partials, n, denom, dst);
   return hipGetLastError();
 }
 

@@ -1,0 +1,104 @@
+// Stateless fused LNCC cost and gradient (include/fa_lncc.h): the gradient
+// kernel of the registration iteration in its gradient-only and loss-only
+// modes, with its own control block and reduction buffers.
+#include <new>
+
+#include "fa_host.h"
+#include "fa_lncc.h"
+
+using fa::fail;
+
+struct fa_lncc_s {
+  hipStream_t stream = nullptr;
+  fa_shape shape{};
+  int64_t n = 0;
+  int window = 5;
+  float eps = 1e-5f;
+  fa::Tiling tg{};
+  fa::Ctl* ctl = nullptr;
+  double* partials = nullptr;   // one per workgroup of the gradient launch
+  double* scratch = nullptr;    // kMeanBlocks doubles for the intensity means
+};
+
+namespace {
+
+void release(fa_lncc h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ctl) (void)hipFree(h->ctl);
+  if (h->partials) (void)hipFree(h->partials);
+  if (h->scratch) (void)hipFree(h->scratch);
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_stream, fa_lncc* out) {
+  if (!out) return fail(FA_EINVAL, "out is NULL");
+  *out = nullptr;
+  FA_TRY(fa::check_shape(shape));
+  if (window < 1 || window > fa::kMaxWindow || window % 2 == 0)
+    return fail(FA_EINVAL, "window must be odd and in [1, 9]");
+  if (!(cc_eps >= 0.0f) || !(cc_eps < 1e30f)) return fail(FA_EINVAL, "cc_eps must be finite and >= 0");
+  fa_lncc h = new (std::nothrow) fa_lncc_s();
+  if (!h) return fail(FA_ENOMEM, "host allocation failed");
+  h->stream = (hipStream_t)hip_stream;
+  h->shape = shape;
+  h->n = fa::voxels(shape);
+  h->window = window;
+  h->eps = cc_eps;
+  h->tg = fa::choose_tiling(shape);
+  const int nb = h->tg.blocks();
+  if (hipMalloc((void**)&h->ctl, sizeof(fa::Ctl)) != hipSuccess ||
+      hipMalloc((void**)&h->partials, (size_t)nb * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->scratch, (size_t)fa::kMeanBlocks * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    release(h);
+    return fail(FA_ENOMEM, "device allocation failed");
+  }
+  const hipError_t e = fa::launch_ctl_init(h->ctl, 0.9f, 0.999f, 0, 0, h->stream);
+  if (e != hipSuccess) {
+    release(h);
+    return fail(FA_EHIP, std::string("launch_ctl_init: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return FA_OK;
+}
+
+fa_status fa_lncc_eval(fa_lncc h, const float* fixed, const float* moving, const float* d,
+                       float* loss_dev, float* grad_dev, const float* grad_scale_dev) {
+  if (!h) return fail(FA_EINVAL, "evaluator is NULL");
+  if (!fixed || !moving || !d) return fail(FA_EINVAL, "fixed, moving and d must not be NULL");
+  if (!loss_dev && !grad_dev) return fail(FA_EINVAL, "loss_dev and grad_dev are both NULL");
+  // global intensity means: LNCC is invariant to a global shift of either
+  // image, and removing it keeps the fp32 window variances well conditioned
+  FA_HIP(fa::launch_mean(fixed, h->n, h->scratch, &h->ctl->shift_i, h->stream));
+  FA_HIP(fa::launch_mean(moving, h->n, h->scratch, &h->ctl->shift_j, h->stream));
+  fa::GradArgs ga{};
+  ga.fixed = fixed;
+  ga.moving = moving;
+  ga.d = d;
+  ga.out = grad_dev;
+  ga.gscale = grad_scale_dev;
+  ga.partials = h->partials;
+  ga.ctl = h->ctl;
+  ga.n0 = h->shape.n0;
+  ga.n1 = h->shape.n1;
+  ga.n2 = h->shape.n2;
+  ga.zc = h->tg.zc;
+  ga.tiles_y = h->tg.tiles_y;
+  ga.tiles_x = h->tg.tiles_x;
+  ga.eps_cc = h->eps;
+  ga.inv_n = (float)(1.0 / (double)h->n);
+  ga.mode = grad_dev ? 1 : 2;
+  FA_HIP(fa::launch_grad(ga, h->window, h->tg, h->stream));
+  if (loss_dev)
+    FA_HIP(fa::launch_partials_ratio(h->partials, h->tg.blocks(), -(double)h->n, loss_dev, h->stream));
+  return FA_OK;
+}
+
+void fa_lncc_destroy(fa_lncc h) { release(h); }
+
+}  // extern "C"

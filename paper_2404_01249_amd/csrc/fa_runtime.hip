@@ -10,35 +10,21 @@
 #include <vector>
 
 #include "fa.h"
+#include "fa_host.h"
 #include "fa_inspect.h"
 #include "fa_internal.h"
 
+using fa::check_shape;
+using fa::choose_tiling;
 using fa::Ctl;
+using fa::fail;
 using fa::Tiling;
+using fa::Tuning;
+using fa::voxels;
 
 namespace {
 
 thread_local std::string g_err;
-
-fa_status fail(fa_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define FA_HIP(call)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(FA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
-  } while (0)
-
-#define FA_TRY(call)                       \
-  do {                                     \
-    fa_status s_ = (call);                 \
-    if (s_ != FA_OK) return s_;            \
-  } while (0)
-
-int64_t voxels(const fa_shape& s) { return (int64_t)s.n0 * s.n1 * s.n2; }
 
 // Sampled Gaussian taps exp(-k^2 / 2 sigma^2), |k| <= ceil(3 sigma),
 // normalised to sum 1 (computed in double).  sigma <= 0 gives the single tap 1.
@@ -59,38 +45,6 @@ std::vector<float> gaussian_taps(float sigma_f) {
 
 int tap_radius(float sigma) { return (int)(gaussian_taps(sigma).size() / 2); }
 
-struct Tuning {
-  int ty = 0, tx = 0, zc = 0, variant = 0;
-};
-
-// In-plane tile and n0 chunking of one streaming launch.  16x32 tiles (8x32
-// when n1 is smaller); the chunk is the longest that keeps the launch within
-// about 512 workgroups (two per CU on 256 CUs), so that every workgroup is
-// resident at once, and at least 2 planes.  (Measured on the 160x192x224
-// pyramid: each level's best chunk length in a sweep of 2..32 planes.)
-Tiling choose_tiling(const fa_shape& s, int halo, const Tuning& tu = Tuning()) {
-  (void)halo;
-  Tiling t;
-  t.tx = 32;
-  t.ty = s.n1 >= 16 ? 16 : 8;
-  if (tu.ty > 0 && tu.tx > 0) {
-    t.ty = tu.ty;
-    t.tx = tu.tx;
-  }
-  t.variant = tu.variant;
-  t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
-  t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
-  const int plane_tiles = t.tiles_y * t.tiles_x;
-  constexpr int kSlots = 512;
-  int zc = (int)(((int64_t)s.n0 * plane_tiles + kSlots - 1) / kSlots);
-  zc = std::max(zc, 2);
-  if (tu.zc > 0) zc = tu.zc;
-  zc = std::min(zc, s.n0);
-  t.zc = zc;
-  t.chunks = (s.n0 + zc - 1) / zc;
-  return t;
-}
-
 struct Level {
   fa_shape shape{};
   int64_t n = 0;
@@ -99,7 +53,7 @@ struct Level {
   float* fixed = nullptr;   // owned unless it aliases the input copy
   float* moving = nullptr;
   bool owns = false;
-  Tiling tg{}, tsg{}, tsw{};  // gradient, sigma_grad and sigma_warp launches
+  Tiling tg{}, tsg{}, tsc{}, tsw{};  // gradient, sigma_grad, composition and sigma_warp launches
 };
 
 }  // namespace
@@ -131,6 +85,7 @@ struct fa_pair_s {
   std::vector<float> wts_host;
   int rg = 0, rw = 0;         // Gaussian radii (sigma_grad, sigma_warp)
   int off_g = 0, off_w = 0;   // offsets of their taps in wts
+  int off_one = 0;            // the single tap 1 (pointwise launches)
   std::vector<int> off_blur;  // per level, pyramid blur taps
   // kernel timing (fa_pair_profile)
   bool profiling = false;
@@ -139,7 +94,7 @@ struct fa_pair_s {
   std::vector<Pending> pending;
   std::vector<double> prof_ms;   // [level][kind]
   std::vector<int> prof_n;
-  Tuning tune[3];   // gradient, sigma_grad, sigma_warp launches
+  Tuning tune[4];   // gradient, sigma_grad, sigma_warp and composition launches
   int cur_level = 0, cur_iter = 0;
   int t_done = 0;      // Adam steps taken (set_state may change it)
   int iters_done = 0;  // schedule iterations run = losses recorded
@@ -200,13 +155,6 @@ fa_status check_params(const fa_params* p) {
   return FA_OK;
 }
 
-fa_status check_shape(const fa_shape& s) {
-  if (s.n0 < 2 || s.n1 < 2 || s.n2 < 2) return fail(FA_ESHAPE, "every dimension must be >= 2");
-  // gathers address one volume with 32-bit signed byte offsets
-  if ((double)s.n0 * s.n1 * s.n2 > 536870911.0)
-    return fail(FA_ESHAPE, "volume too large: n0*n1*n2 must be < 2^29");
-  return FA_OK;
-}
 
 fa_shape level_shape(const fa_shape& s, float scale) {
   const double sc = (double)scale;
@@ -297,22 +245,30 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   gs.eta = P->p.eta;
   gs.inv_n = (float)(1.0 / (double)L.n);
 
-  fa::GaussArgs g1 = gs;  // M = max |G * a|
+  fa::GaussArgs g1 = gs;  // s = G * a into tmp, M = max |s|
   g1.in = P->a;
+  g1.out = P->tmp;
   g1.wts = P->wts + P->off_g;
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
-  FA_HIP(fa::launch_gauss(g1, P->rg, fa::EPI_MAXNORM, L.tsg, P->stream));
+  FA_HIP(fa::launch_gauss(g1, P->rg, fa::EPI_SMOOTH_MAX, L.tsg, P->stream));
   if (P->profiling) FA_HIP(hipEventRecord(pe.e[2], P->stream));
 
-  fa::GaussArgs g2 = g1;  // d' = u + d(x + u)
+  // d' = u + d(x + u) with u = -eta s / (2M), in place over s: the single-tap
+  // launch reads s only at the voxel it writes, one plane ahead
+  fa::GaussArgs g2 = gs;
+  g2.in = P->tmp;
   g2.out = P->tmp;
   g2.d = P->d;
+  g2.wts = P->wts + P->off_one;
+  g2.zc = L.tsc.zc;
+  g2.tiles_y = L.tsc.tiles_y;
+  g2.tiles_x = L.tsc.tiles_x;
   // |u| <= eta / 2: with eta <= 2 the sample stays within one voxel, and d
   // is staged in LDS instead of gathered
   const int epi_c = P->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE;
-  FA_HIP(fa::launch_gauss(g2, P->rg, epi_c, L.tsg, P->stream));
+  FA_HIP(fa::launch_gauss(g2, 0, epi_c, L.tsc, P->stream));
   if (P->profiling) FA_HIP(hipEventRecord(pe.e[3], P->stream));
 
   fa::GaussArgs g3 = gs;  // d = G * d'; record loss, advance t
@@ -377,6 +333,50 @@ bool schedule_done(const fa_pair P) {
 
 }  // namespace
 
+namespace fa {
+
+fa_status fail(fa_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+fa_status check_shape(const fa_shape& s) {
+  if (s.n0 < 2 || s.n1 < 2 || s.n2 < 2) return fail(FA_ESHAPE, "every dimension must be >= 2");
+  // gathers address one volume with 32-bit signed byte offsets
+  if ((double)s.n0 * s.n1 * s.n2 > 536870911.0)
+    return fail(FA_ESHAPE, "volume too large: n0*n1*n2 must be < 2^29");
+  return FA_OK;
+}
+
+// In-plane tile and n0 chunking of one streaming launch.  16x32 tiles (8x32
+// when n1 is smaller); the chunk is the longest that keeps the launch within
+// about 512 workgroups (two per CU on 256 CUs), so that every workgroup is
+// resident at once, and at least 2 planes.  (Measured on the 160x192x224
+// pyramid: each level's best chunk length in a sweep of 2..32 planes.)
+Tiling choose_tiling(const fa_shape& s, const Tuning& tu) {
+  Tiling t;
+  t.tx = 32;
+  t.ty = s.n1 >= 16 ? 16 : 8;
+  if (tu.ty > 0 && tu.tx > 0) {
+    t.ty = tu.ty;
+    t.tx = tu.tx;
+  }
+  t.variant = tu.variant;
+  t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
+  t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
+  const int plane_tiles = t.tiles_y * t.tiles_x;
+  constexpr int kSlots = 512;
+  int zc = (int)(((int64_t)s.n0 * plane_tiles + kSlots - 1) / kSlots);
+  zc = std::max(zc, 2);
+  if (tu.zc > 0) zc = tu.zc;
+  zc = std::min(zc, s.n0);
+  t.zc = zc;
+  t.chunks = (s.n0 + zc - 1) / zc;
+  return t;
+}
+
+}  // namespace fa
+
 extern "C" {
 
 const char* fa_last_error(void) { return g_err.c_str(); }
@@ -437,7 +437,6 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
   std::vector<Level> lv(n_levels);
   int64_t total_iters = 0, nmax = 0;
   int pmax = 1;
-  const int r = P->p.cc_window / 2;
   P->rg = tap_radius(P->p.sigma_grad);
   P->rw = tap_radius(P->p.sigma_warp);
   for (int i = 0; i < n_levels; ++i) {
@@ -450,9 +449,10 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     lv[i].n = voxels(lv[i].shape);
     if (lv[i].shape.n0 < 2 || lv[i].shape.n1 < 2 || lv[i].shape.n2 < 2)
       return fail(FA_ESHAPE, "level " + std::to_string(i) + " has a dimension < 2");
-    lv[i].tg = choose_tiling(lv[i].shape, 2 * r, P->tune[0]);
-    lv[i].tsg = choose_tiling(lv[i].shape, P->rg, P->tune[1]);
-    lv[i].tsw = choose_tiling(lv[i].shape, P->rw, P->tune[2]);
+    lv[i].tg = choose_tiling(lv[i].shape, P->tune[0]);
+    lv[i].tsg = choose_tiling(lv[i].shape, P->tune[1]);
+    lv[i].tsw = choose_tiling(lv[i].shape, P->tune[2]);
+    lv[i].tsc = choose_tiling(lv[i].shape, P->tune[3]);
     total_iters += iters[i];
     nmax = std::max(nmax, lv[i].n);
     pmax = std::max(pmax, lv[i].tg.blocks());
@@ -474,6 +474,7 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
   };
   P->off_g = push(gaussian_taps(P->p.sigma_grad));
   P->off_w = push(gaussian_taps(P->p.sigma_warp));
+  P->off_one = push(std::vector<float>{1.0f});
   P->off_blur.assign(n_levels, 0);
   for (int i = 0; i < n_levels; ++i) P->off_blur[i] = push(gaussian_taps(lv[i].scale / 2.0f));
   if (P->wts) (void)hipFree(P->wts);
@@ -719,7 +720,7 @@ fa_status fa_pair_get_level_image(fa_pair P, int level, int which, float* dev_ou
 
 fa_status fa_pair_set_tuning(fa_pair P, int kind, int ty, int tx, int zc, int variant) {
   if (!P) return fail(FA_EINVAL, "pair is NULL");
-  if (kind < 0 || kind > 2) return fail(FA_EINVAL, "kind must be 0, 1 or 2");
+  if (kind < 0 || kind > 3) return fail(FA_EINVAL, "kind must be 0, 1, 2 or 3");
   const bool autotile = ty == 0 && tx == 0;
   if (!autotile && !(kind == 0 ? fa::grad_tile_supported(ty, tx) : fa::gauss_tile_supported(ty, tx)))
     return fail(FA_EINVAL, "unsupported tile shape");

@@ -1,4 +1,5 @@
-"""ctypes binding of the C ABI in include/fa.h and include/fa_inspect.h.
+"""ctypes binding of the C ABI in include/fa.h, include/fa_inspect.h,
+include/fa_lncc.h and include/fa_eval.h.
 
 Each function has the name of the C entry point it wraps and only marshals
 arguments: torch tensors become device pointers, the stream becomes its HIP
@@ -42,6 +43,8 @@ _P = ctypes.c_void_p
 _I = ctypes.c_int
 _IP = ctypes.POINTER(ctypes.c_int)
 _FP = ctypes.POINTER(ctypes.c_float)
+_I64 = ctypes.c_int64
+_I64P = ctypes.POINTER(ctypes.c_int64)
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -64,6 +67,12 @@ SIGNATURES = {
     "fa_pair_profile": (_I, [_P, _I]),
     "fa_pair_set_tuning": (_I, [_P, _I, _I, _I, _I, _I]),
     "fa_pair_get_profile": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_double), _IP]),
+    "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
+    "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "fa_lncc_destroy": (None, [_P]),
+    "fa_warp_labels": (_I, [_P, _P, fa_shape, _P, _P]),
+    "fa_label_overlap": (_I, [_P, _P, _I64, _I, _I64P, _P]),
+    "fa_jacobian_det": (_I, [_P, fa_shape, _P, _I64P, _I64P, _P]),
 }
 
 _lib = None
@@ -99,6 +108,19 @@ def _ptr(t) -> int | None:
         raise ValueError("tensor must be on the GPU")
     if t.dtype.itemsize != 4 or not t.is_floating_point():
         raise ValueError("tensor must be float32")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _ptr_typed(t, dtype_name: str) -> int | None:
+    """Device pointer of a contiguous GPU tensor of the given torch dtype (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise ValueError(f"tensor must be {dtype_name}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return t.data_ptr()
@@ -220,3 +242,50 @@ def fa_pair_get_profile(pair: int, level: int, kind: int) -> tuple[float, int]:
 
 def fa_pair_set_tuning(pair: int, kind: int, ty: int = 0, tx: int = 0, zc: int = 0, variant: int = 0):
     _check(load_library().fa_pair_set_tuning(pair, int(kind), int(ty), int(tx), int(zc), int(variant)))
+
+
+# ---- include/fa_lncc.h --------------------------------------------------------
+
+def fa_lncc_create(shape, window: int = 5, cc_eps: float = 1e-5, stream=None) -> int:
+    h = _P()
+    _check(load_library().fa_lncc_create(fa_shape(*[int(x) for x in shape]), int(window), float(cc_eps),
+                                         _stream_handle(stream), ctypes.byref(h)))
+    return h.value
+
+
+def fa_lncc_eval(h: int, fixed, moving, d, loss_dev=None, grad_dev=None, grad_scale_dev=None):
+    _check(load_library().fa_lncc_eval(h, _ptr(fixed), _ptr(moving), _ptr(d), _ptr(loss_dev), _ptr(grad_dev),
+                                       _ptr(grad_scale_dev)))
+
+
+def fa_lncc_destroy(h: int):
+    if h:
+        load_library().fa_lncc_destroy(h)
+
+
+# ---- include/fa_eval.h --------------------------------------------------------
+
+def fa_warp_labels(labels, d, out, stream=None):
+    shape = fa_shape(*[int(x) for x in labels.shape])
+    _check(load_library().fa_warp_labels(_ptr_typed(labels, "int8"), _ptr(d), shape, _ptr_typed(out, "int8"),
+                                         _stream_handle(stream)))
+
+
+def fa_label_overlap(a, b, n_classes: int, stream=None) -> np.ndarray:
+    if a.numel() != b.numel():
+        raise ValueError("a and b must have the same number of voxels")
+    counts = np.zeros(3 * int(n_classes), dtype=np.int64)
+    _check(load_library().fa_label_overlap(_ptr_typed(a, "int8"), _ptr_typed(b, "int8"), int(a.numel()),
+                                           int(n_classes), counts.ctypes.data_as(_I64P), _stream_handle(stream)))
+    return counts.reshape(int(n_classes), 3)
+
+
+def fa_jacobian_det(d, det_out=None, count: bool = True, stream=None) -> tuple[int, int]:
+    if d.dim() != 4 or d.shape[0] != 3:
+        raise ValueError("d must be (3, n0, n1, n2)")
+    shape = fa_shape(*[int(x) for x in d.shape[1:]])
+    nonpos, interior = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load_library().fa_jacobian_det(_ptr(d), shape, _ptr_typed(det_out, "float64"),
+                                          ctypes.byref(nonpos) if count else None, ctypes.byref(interior),
+                                          _stream_handle(stream)))
+    return nonpos.value, interior.value
