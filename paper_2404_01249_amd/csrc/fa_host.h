@@ -27,9 +27,12 @@ struct Tuning {
   int ty = 0, tx = 0, zc = 0, variant = 0;
 };
 
-// In-plane tile and n0 chunking of one streaming launch over a volume of
-// shape s.
-Tiling choose_tiling(const fa_shape& s, const Tuning& tu = Tuning());
+// The streaming kernels whose launch shape is chosen per level.
+enum KernelKind { KIND_GRAD = 0, KIND_SMOOTH_MAX = 1, KIND_WARP_SMOOTH = 2, KIND_COMPOSE = 3 };
+
+// In-plane tile and n0 chunking of one launch of kernel `kind` over a volume
+// of shape s (tu overrides the automatic choice).
+Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu = Tuning());
 
 }  // namespace fa
 

@@ -528,9 +528,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
 #pragma unroll
       for (int k = 0; k < CPT1; ++k) {
         if (cuse[k]) {
-          float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+          // sums start from the first term: 0 + x is not foldable in IEEE
+          // arithmetic (signed zero) and would cost an add per sum
+          const float i0 = ringI[k][0], j0 = ringJ[k][0];
+          float s0 = i0, s1 = j0, s2 = i0 * i0, s3 = j0 * j0, s4 = i0 * j0;
 #pragma unroll
-          for (int j = 0; j < W; ++j) {
+          for (int j = 1; j < W; ++j) {
             const float i_ = ringI[k][j], j_ = ringJ[k][j];
             s0 += i_;
             s1 += j_;
@@ -550,9 +553,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
       for (int c = tid; c < XS1; c += NT) {
         const int yy = c / E2X, xo = c - yy * E2X;
         const float* src = buf + yy * E1X + xo;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+        float s0 = src[0], s1 = src[E1], s2 = src[2 * E1], s3 = src[3 * E1], s4 = src[4 * E1];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
+        for (int k = 1; k < W; ++k) {
           s0 += src[k];
           s1 += src[E1 + k];
           s2 += src[2 * E1 + k];
@@ -575,9 +578,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
         const int c = tid + k2 * NT;
         if (c >= E2) break;
         const float* src = bufx + e2off[k2];
-        float SI = 0.f, SJ = 0.f, SII = 0.f, SJJ = 0.f, SIJ = 0.f;
+        float SI = src[0], SJ = src[XS1], SII = src[2 * XS1], SJJ = src[3 * XS1], SIJ = src[4 * XS1];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
+        for (int k = 1; k < W; ++k) {
           SI += src[k * E2X];
           SJ += src[XS1 + k * E2X];
           SII += src[2 * XS1 + k * E2X];
@@ -612,9 +615,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
       for (int c = tid; c < XS2; c += NT) {
         const int yy = c / TX, xo = c - yy * TX;
         const float* src = buf + yy * E2X + xo;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        float s0 = src[0], s1 = src[E2], s2 = src[2 * E2];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
+        for (int k = 1; k < W; ++k) {
           s0 += src[k];
           s1 += src[E2 + k];
           s2 += src[2 * E2 + k];
@@ -626,9 +629,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
       __syncthreads();
       {
         const float* src = bufx + oy * TX + ox;
-        float sa = 0.f, sb = 0.f, sc = 0.f;
+        float sa = src[0], sb = src[XS2], sc = src[2 * XS2];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
+        for (int k = 1; k < W; ++k) {
           sa += src[k * TX];
           sb += src[XS2 + k * TX];
           sc += src[2 * XS2 + k * TX];
@@ -653,9 +656,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
             pv[q] = A.v[q * N + idx];
           }
         }
-        float SA = 0.f, SB = 0.f, SC = 0.f;
+        float SA = ringA[0], SB = ringB[0], SC = ringC[0];
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
+        for (int j = 1; j < W; ++j) {
           SA += ringA[j];
           SB += ringB[j];
           SC += ringC[j];
@@ -733,6 +736,38 @@ __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)
 // before the current plane's passes; the composition epilogue issues its
 // gathers of d in one plane step and consumes them in the next.
 // ---------------------------------------------------------------------------
+// End of an iteration, in the last launch: the last workgroup to finish
+// records the iteration's loss from the gradient kernel's partials and
+// advances the Adam step count.  No workgroup of the launch reads the control
+// block, so the update cannot race.
+template <int NT>
+__device__ __forceinline__ void finish_iteration(const GaussArgs& A, double* red, int* is_last) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&A.ctl->ticket, 1u);
+    *is_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (*is_last) {
+    __threadfence();
+    double s = 0.0;
+    for (int i = tid; i < A.n_partials; i += NT) s += A.partials[i];
+    s = block_sum<NT>(s, red);
+    if (tid == 0) {
+      const int t = A.ctl->t;
+      const int it = A.ctl->iter;
+      if (A.loss_hist && it >= 0 && it < A.loss_cap) A.loss_hist[it] = (float)(-s * (double)A.inv_n);
+      A.ctl->iter = it + 1;
+      A.ctl->t = t + 1;
+      A.ctl->bc1 = (float)(1.0 - pow((double)A.ctl->beta1, (double)(t + 1)));
+      A.ctl->bc2 = (float)(1.0 - pow((double)A.ctl->beta2, (double)(t + 1)));
+      A.ctl->ticket = 0u;
+    }
+  }
+}
+
 template <int R, int TY, int TX, int EPI>
 __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   constexpr int L = 2 * R + 1;
@@ -891,9 +926,9 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
     for (int c = tid; c < XS; c += NT) {
       const int yy = c / TX, xo = c - yy * TX;
       const float* src = buf + yy * EX + xo;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      float s0 = w[0] * src[0], s1 = w[0] * src[E], s2 = w[0] * src[2 * E];
 #pragma unroll
-      for (int k = 0; k < L; ++k) {
+      for (int k = 1; k < L; ++k) {
         s0 += w[k] * src[k];
         s1 += w[k] * src[E + k];
         s2 += w[k] * src[2 * E + k];
@@ -906,9 +941,9 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
     if (EPI == EPI_COMPOSE) finish_compose();
     {
       const float* src = bufx + oy * TX + ox;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      float s0 = w[0] * src[0], s1 = w[0] * src[XS], s2 = w[0] * src[2 * XS];
 #pragma unroll
-      for (int k = 0; k < L; ++k) {
+      for (int k = 1; k < L; ++k) {
         s0 += w[k] * src[k * TX];
         s1 += w[k] * src[XS + k * TX];
         s2 += w[k] * src[2 * XS + k * TX];
@@ -926,9 +961,9 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
     }
     const int zo = zin - R;
     if (zo >= z0 && out_col) {
-      float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+      float v0 = w[0] * ring[0][0], v1 = w[0] * ring[1][0], v2 = w[0] * ring[2][0];
 #pragma unroll
-      for (int j = 0; j < L; ++j) {
+      for (int j = 1; j < L; ++j) {
         v0 += w[j] * ring[0][j];
         v1 += w[j] * ring[1][j];
         v2 += w[j] * ring[2][j];
@@ -991,34 +1026,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
   }
-  if (EPI == EPI_STORE_FINAL) {
-    // The last workgroup to finish records the iteration's loss and advances
-    // the Adam step count; no workgroup of this launch reads the control
-    // block, so the update cannot race.
-    __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const unsigned prev = atomicAdd(&A.ctl->ticket, 1u);
-      is_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (is_last) {
-      __threadfence();
-      double s = 0.0;
-      for (int i = tid; i < A.n_partials; i += NT) s += A.partials[i];
-      s = block_sum<NT>(s, red);
-      if (tid == 0) {
-        const int t = A.ctl->t;
-        const int it = A.ctl->iter;
-        if (A.loss_hist && it >= 0 && it < A.loss_cap) A.loss_hist[it] = (float)(-s * (double)A.inv_n);
-        A.ctl->iter = it + 1;
-        A.ctl->t = t + 1;
-        A.ctl->bc1 = (float)(1.0 - pow((double)A.ctl->beta1, (double)(t + 1)));
-        A.ctl->bc2 = (float)(1.0 - pow((double)A.ctl->beta2, (double)(t + 1)));
-        A.ctl->ticket = 0u;
-      }
-    }
-  }
+  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last);
 }
 
 // ---------------------------------------------------------------------------
@@ -1235,6 +1243,7 @@ hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tili
   if (t.ty == 8 && t.tx == 64) return gauss_launch_tile<8, 64>(a, radius, epilogue, t, s);
   return hipErrorInvalidValue;
 }
+
 
 static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 

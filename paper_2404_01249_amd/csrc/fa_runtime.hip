@@ -72,7 +72,7 @@ struct fa_pair_s {
   float* m = nullptr;
   float* v = nullptr;
   float* a = nullptr;         // Adam direction
-  float* tmp = nullptr;       // composed displacement before sigma_warp
+  float* tmp = nullptr;       // smoothed direction s, then the composed d'
   float* blur0 = nullptr;     // pyramid scratch (input size)
   float* blur1 = nullptr;
   Ctl* ctl = nullptr;
@@ -348,12 +348,18 @@ fa_status check_shape(const fa_shape& s) {
   return FA_OK;
 }
 
-// In-plane tile and n0 chunking of one streaming launch.  16x32 tiles (8x32
-// when n1 is smaller); the chunk is the longest that keeps the launch within
-// about 512 workgroups (two per CU on 256 CUs), so that every workgroup is
-// resident at once, and at least 2 planes.  (Measured on the 160x192x224
-// pyramid: each level's best chunk length in a sweep of 2..32 planes.)
-Tiling choose_tiling(const fa_shape& s, const Tuning& tu) {
+// In-plane tile and n0 chunking of one streaming launch: 16x32 tiles (8x32
+// when n1 is smaller) and the longest chunk that keeps the launch within a
+// number of workgroups the GPU holds resident at once, so that no workgroup
+// waits for another to finish, and at least a minimum chunk.  The gradient
+// kernel holds two workgroups per CU (512 on 256 CUs); the sigma_grad
+// smoothing kernel, with fewer registers, holds four.  The 2R-plane halos of
+// the two smoothing kernels make chunks below 4 planes wasteful.  (Measured
+// on the 160x192x224 pyramid: each level's time over chunks of 1 to 40
+// planes.)
+Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu) {
+  static const int kSlots[4] = {512, 1024, 512, 512};
+  static const int kMinChunk[4] = {1, 4, 4, 1};
   Tiling t;
   t.tx = 32;
   t.ty = s.n1 >= 16 ? 16 : 8;
@@ -365,9 +371,8 @@ Tiling choose_tiling(const fa_shape& s, const Tuning& tu) {
   t.tiles_y = (s.n1 + t.ty - 1) / t.ty;
   t.tiles_x = (s.n2 + t.tx - 1) / t.tx;
   const int plane_tiles = t.tiles_y * t.tiles_x;
-  constexpr int kSlots = 512;
-  int zc = (int)(((int64_t)s.n0 * plane_tiles + kSlots - 1) / kSlots);
-  zc = std::max(zc, 2);
+  int zc = (int)(((int64_t)s.n0 * plane_tiles + kSlots[kind] - 1) / kSlots[kind]);
+  zc = std::max(zc, kMinChunk[kind]);
   if (tu.zc > 0) zc = tu.zc;
   zc = std::min(zc, s.n0);
   t.zc = zc;
@@ -449,10 +454,10 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     lv[i].n = voxels(lv[i].shape);
     if (lv[i].shape.n0 < 2 || lv[i].shape.n1 < 2 || lv[i].shape.n2 < 2)
       return fail(FA_ESHAPE, "level " + std::to_string(i) + " has a dimension < 2");
-    lv[i].tg = choose_tiling(lv[i].shape, P->tune[0]);
-    lv[i].tsg = choose_tiling(lv[i].shape, P->tune[1]);
-    lv[i].tsw = choose_tiling(lv[i].shape, P->tune[2]);
-    lv[i].tsc = choose_tiling(lv[i].shape, P->tune[3]);
+    lv[i].tg = choose_tiling(lv[i].shape, fa::KIND_GRAD, P->tune[0]);
+    lv[i].tsg = choose_tiling(lv[i].shape, fa::KIND_SMOOTH_MAX, P->tune[1]);
+    lv[i].tsw = choose_tiling(lv[i].shape, fa::KIND_WARP_SMOOTH, P->tune[2]);
+    lv[i].tsc = choose_tiling(lv[i].shape, fa::KIND_COMPOSE, P->tune[3]);
     total_iters += iters[i];
     nmax = std::max(nmax, lv[i].n);
     pmax = std::max(pmax, lv[i].tg.blocks());
