@@ -69,13 +69,20 @@ k_overlap_partial(const int8_t* __restrict__ a, const int8_t* __restrict__ b, in
   for (int j = threadIdx.x; j < 3 * nc; j += kThreads) part[(size_t)blockIdx.x * 3 * nc + j] = cnt[j];
 }
 
+// One workgroup per counter: the sum over the workgroups' partial counts.
 __global__ void __launch_bounds__(kThreads)
 k_overlap_final(const unsigned* __restrict__ part, int nblocks, int nc, unsigned long long* __restrict__ out) {
-  for (int j = threadIdx.x; j < 3 * nc; j += kThreads) {
-    unsigned long long s = 0ull;
-    for (int k = 0; k < nblocks; ++k) s += part[(size_t)k * 3 * nc + j];
-    out[j] = s;
+  __shared__ unsigned long long red[kThreads];
+  const int j = blockIdx.x;
+  unsigned long long s = 0ull;
+  for (int k = threadIdx.x; k < nblocks; k += kThreads) s += part[(size_t)k * 3 * nc + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[j] = red[0];
 }
 
 // det(I + grad d) by central differences at interior voxels, in double.
@@ -178,7 +185,7 @@ fa_status fa_label_overlap(const int8_t* a_dev, const int8_t* b_dev, int64_t n, 
   unsigned long long* tot = (unsigned long long*)((char*)sc.p + part_bytes);
   hipLaunchKernelGGL(k_overlap_partial, dim3(nb), dim3(kThreads), 0, s, a_dev, b_dev, n, n_classes, part);
   FA_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kThreads), 0, s, part, nb, n_classes, tot);
+  hipLaunchKernelGGL(k_overlap_final, dim3(3 * n_classes), dim3(kThreads), 0, s, part, nb, n_classes, tot);
   FA_HIP(hipGetLastError());
   std::vector<unsigned long long> h((size_t)3 * n_classes);
   FA_HIP(hipMemcpyAsync(h.data(), tot, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
