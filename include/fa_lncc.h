@@ -34,8 +34,10 @@ extern "C" {
 typedef struct fa_lncc_s* fa_lncc;   /* opaque; owns its reduction buffers */
 
 /* Create an evaluator for volumes of `shape` (every dimension >= 2,
- * n0*n1*n2 < 2^29), window w (odd, 1..9) and eps >= 0.  Allocates a few KB of
- * device memory; work is enqueued on `hip_stream` (NULL = null stream). */
+ * n0*n1*n2 < 2^29), window w (odd, 1..9) and eps >= 0.  Allocates a copy of
+ * the moving image with a two-voxel zero border, (n0+4)(n1+4)(n2+4) floats,
+ * plus a few KB of device memory; work is enqueued on `hip_stream`
+ * (NULL = null stream). */
 fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_stream, fa_lncc* out);
 
 /* Evaluate at (fixed, moving, d), all device pointers of the evaluator's shape.

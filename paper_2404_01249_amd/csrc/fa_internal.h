@@ -35,7 +35,7 @@ struct Tiling {
 // ---- fused gradient (+ Adam) kernel -------------------------------------
 struct GradArgs {
   const float* fixed;
-  const float* moving;
+  const float* moving_pad;   // moving image with a zero border of kPad voxels
   const float* d;        // [3][N]
   float* m;              // [3][N] (Adam mode)
   float* v;              // [3][N]
@@ -85,6 +85,8 @@ struct GaussArgs {
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s);
 hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s);
 hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s);
+// out = in with a zero border of kPad voxels (padded_voxels(n0, n1, n2) floats).
+hipError_t launch_pad(const float* in, float* out, int n0, int n1, int n2, hipStream_t s);
 hipError_t launch_blur_axis(const float* in, float* out, int n0, int n1, int n2, int axis,
                             const float* wts, int radius, hipStream_t s);
 hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int nin2,
@@ -109,6 +111,11 @@ size_t grad_lds_bytes(int window, int ty, int tx);
 size_t gauss_lds_bytes(int radius, int ty, int tx);
 
 constexpr int kMaxWindow = 9;
+// Zero border of the padded moving image the gradient kernel samples.
+constexpr int kPad = 2;
+inline int64_t padded_voxels(int n0, int n1, int n2) {
+  return (int64_t)(n0 + 2 * kPad) * (n1 + 2 * kPad) * (n2 + 2 * kPad);
+}
 constexpr int kMaxRadius = 6;
 
 }  // namespace fa

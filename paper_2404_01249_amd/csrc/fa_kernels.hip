@@ -18,6 +18,8 @@
 // parts are separable passes over halo tiles staged in LDS.  The path is a
 // stencil-and-gather workload bound by HBM bandwidth; there is no dense
 // contraction, so no MFMA.
+#include <algorithm>
+
 #include "fa_internal.h"
 
 namespace fa {
@@ -256,6 +258,43 @@ __device__ __forceinline__ Cell8 cell8_at(int n0, int n1, int n2, int z, int y, 
   return c;
 }
 
+// The same for a volume stored with a zero border of kPad voxels on every
+// side (padded strides).  The cell is clamped to [-kPad, n], so every corner
+// lies in the padded volume, and a corner off the grid reads a zero of the
+// border: no mask is needed (the mask is constant, and the selects fold
+// away).  A sample clamped this way lies wholly in the border, so its value
+// and derivative are 0, as with the masked form.
+__device__ __forceinline__ void axis_offsets_pad(int x, float dd, int n, int stride_bytes, unsigned& lo,
+                                                 unsigned& hi, float& t) {
+  dd = fminf(fmaxf(dd, (float)(-x - kPad)), (float)(n - x));
+  const float f = floorf(dd);
+  const int i = x + kPad + (int)f;   // padded index, in [0, n + kPad]
+  t = dd - f;
+  lo = (unsigned)(i * stride_bytes);
+  hi = lo + (unsigned)stride_bytes;
+}
+
+__device__ __forceinline__ Cell8 cell8_pad(int n0, int n1, int n2, int z, int y, int x, float d0, float d1,
+                                           float d2) {
+  Cell8 c;
+  const int p2 = n2 + 2 * kPad, p1 = n1 + 2 * kPad;
+  unsigned l0, h0, l1, h1, l2, h2;
+  axis_offsets_pad(z, d0, n0, p1 * p2 * 4, l0, h0, c.t0);
+  axis_offsets_pad(y, d1, n1, p2 * 4, l1, h1, c.t1);
+  axis_offsets_pad(x, d2, n2, 4, l2, h2, c.t2);
+  const unsigned a00 = l0 + l1, a01 = l0 + h1, a10 = h0 + l1, a11 = h0 + h1;
+  c.off[0] = a00 + l2;
+  c.off[1] = a00 + h2;
+  c.off[2] = a01 + l2;
+  c.off[3] = a01 + h2;
+  c.off[4] = a10 + l2;
+  c.off[5] = a10 + h2;
+  c.off[6] = a11 + l2;
+  c.off[7] = a11 + h2;
+  c.mask = 0xFFu;
+  return c;
+}
+
 // Eight corner values of a trilinear sample (loaded; consumed later so that
 // issuing the loads does not wait for them).
 struct Gather {
@@ -471,8 +510,8 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
   auto issue_gather = [&](int z, int k) {
     gv[k] = z >= 0 && z < n0 && cin[k];
     if (gv[k]) {
-      const Cell8 c = cell8_at(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
-      gather_issue(A.moving, c, gq[k]);
+      const Cell8 c = cell8_pad(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
+      gather_issue(A.moving_pad, c, gq[k]);
       nxI[k] = nf[k] - si;
     }
   };
@@ -1032,6 +1071,20 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
 // ---------------------------------------------------------------------------
 // Off-loop kernels: pyramid blur and resampling, warp, fills, layout copies.
 // ---------------------------------------------------------------------------
+// Copy of a volume with a zero border of kPad voxels on every side.
+__global__ void k_pad(const float* __restrict__ in, float* __restrict__ out, int n0, int n1, int n2) {
+  const int p0 = n0 + 2 * kPad, p1 = n1 + 2 * kPad, p2 = n2 + 2 * kPad;
+  const int64_t total = (int64_t)p0 * p1 * p2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % p2) - kPad;
+    const int64_t t = i / p2;
+    const int y = (int)(t % p1) - kPad;
+    const int z = (int)(t / p1) - kPad;
+    const bool in_grid = z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2;
+    out[i] = in_grid ? in[((int64_t)z * n1 + y) * n2 + x] : 0.0f;
+  }
+}
+
 __global__ void k_fill(float* __restrict__ p, float value, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = value;
@@ -1246,6 +1299,13 @@ hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tili
 
 
 static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_pad(const float* in, float* out, int n0, int n1, int n2, hipStream_t s) {
+  const int64_t total = (int64_t)(n0 + 2 * kPad) * (n1 + 2 * kPad) * (n2 + 2 * kPad);
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pad, dim3(blocks), dim3(256), 0, s, in, out, n0, n1, n2);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

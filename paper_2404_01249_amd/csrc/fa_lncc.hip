@@ -1,6 +1,7 @@
 // Stateless fused LNCC cost and gradient (include/fa_lncc.h): the gradient
 // kernel of the registration iteration in its gradient-only and loss-only
-// modes, with its own control block and reduction buffers.
+// modes, with its own control block, reduction buffers and padded copy of the
+// moving image.
 #include <new>
 
 #include "fa_host.h"
@@ -18,6 +19,7 @@ struct fa_lncc_s {
   fa::Ctl* ctl = nullptr;
   double* partials = nullptr;   // one per workgroup of the gradient launch
   double* scratch = nullptr;    // kMeanBlocks doubles for the intensity means
+  float* moving_pad = nullptr;  // the moving image with a zero border, refreshed per call
 };
 
 namespace {
@@ -28,6 +30,7 @@ void release(fa_lncc h) {
   if (h->ctl) (void)hipFree(h->ctl);
   if (h->partials) (void)hipFree(h->partials);
   if (h->scratch) (void)hipFree(h->scratch);
+  if (h->moving_pad) (void)hipFree(h->moving_pad);
   delete h;
 }
 
@@ -53,7 +56,9 @@ fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_str
   const int nb = h->tg.blocks();
   if (hipMalloc((void**)&h->ctl, sizeof(fa::Ctl)) != hipSuccess ||
       hipMalloc((void**)&h->partials, (size_t)nb * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&h->scratch, (size_t)fa::kMeanBlocks * sizeof(double)) != hipSuccess) {
+      hipMalloc((void**)&h->scratch, (size_t)fa::kMeanBlocks * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->moving_pad, (size_t)fa::padded_voxels(shape.n0, shape.n1, shape.n2) * sizeof(float)) !=
+          hipSuccess) {
     (void)hipGetLastError();
     release(h);
     return fail(FA_ENOMEM, "device allocation failed");
@@ -76,9 +81,10 @@ fa_status fa_lncc_eval(fa_lncc h, const float* fixed, const float* moving, const
   // image, and removing it keeps the fp32 window variances well conditioned
   FA_HIP(fa::launch_mean(fixed, h->n, h->scratch, &h->ctl->shift_i, h->stream));
   FA_HIP(fa::launch_mean(moving, h->n, h->scratch, &h->ctl->shift_j, h->stream));
+  FA_HIP(fa::launch_pad(moving, h->moving_pad, h->shape.n0, h->shape.n1, h->shape.n2, h->stream));
   fa::GradArgs ga{};
   ga.fixed = fixed;
-  ga.moving = moving;
+  ga.moving_pad = h->moving_pad;
   ga.d = d;
   ga.out = grad_dev;
   ga.gscale = grad_scale_dev;

@@ -52,6 +52,7 @@ struct Level {
   int iters = 0;
   float* fixed = nullptr;   // owned unless it aliases the input copy
   float* moving = nullptr;
+  float* moving_pad = nullptr;  // moving with a zero border (owned), sampled by the gradient kernel
   bool owns = false;
   Tiling tg{}, tsg{}, tsc{}, tsw{};  // gradient, sigma_grad, composition and sigma_warp launches
 };
@@ -109,6 +110,7 @@ void free_levels(fa_pair P) {
       (void)hipFree(L.fixed);
       (void)hipFree(L.moving);
     }
+    if (L.moving_pad) (void)hipFree(L.moving_pad);
   }
   P->levels.clear();
 }
@@ -215,7 +217,7 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   }
   fa::GradArgs ga{};
   ga.fixed = L.fixed;
-  ga.moving = L.moving;
+  ga.moving_pad = L.moving_pad;
   ga.d = P->d;
   ga.m = P->m;
   ga.v = P->v;
@@ -345,6 +347,9 @@ fa_status check_shape(const fa_shape& s) {
   // gathers address one volume with 32-bit signed byte offsets
   if ((double)s.n0 * s.n1 * s.n2 > 536870911.0)
     return fail(FA_ESHAPE, "volume too large: n0*n1*n2 must be < 2^29");
+  // the gradient kernel addresses the padded moving image with 32-bit byte offsets
+  if ((double)(s.n0 + 2 * kPad) * (s.n1 + 2 * kPad) * (s.n2 + 2 * kPad) > 1073741823.0)
+    return fail(FA_ESHAPE, "volume too large: the padded volume (n+4 per axis) must hold < 2^30 voxels");
   return FA_OK;
 }
 
@@ -540,6 +545,10 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     FA_TRY(build_level_image(P, P->in_fixed, L.fixed, L, P->off_blur[i]));
     FA_TRY(build_level_image(P, P->in_moving, L.moving, L, P->off_blur[i]));
   }
+  for (auto& L : P->levels) {
+    FA_TRY(dalloc(&L.moving_pad, (size_t)fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2), "padded moving"));
+    FA_HIP(fa::launch_pad(L.moving, L.moving_pad, L.shape.n0, L.shape.n1, L.shape.n2, P->stream));
+  }
 
   // State: phi = id, m = v = 0, t = 0.
   const int64_t n0 = P->levels[0].n;
@@ -666,7 +675,7 @@ fa_status fa_pair_eval_gradient(fa_pair P, float* g_dev, float* loss_host) {
   const Level& L = P->levels[P->cur_level];
   fa::GradArgs ga{};
   ga.fixed = L.fixed;
-  ga.moving = L.moving;
+  ga.moving_pad = L.moving_pad;
   ga.d = P->d;
   ga.out = g_dev ? g_dev : P->tmp;
   ga.partials = P->partials;
