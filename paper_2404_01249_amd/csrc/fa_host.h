@@ -31,8 +31,10 @@ struct Tuning {
 enum KernelKind { KIND_GRAD = 0, KIND_SMOOTH_MAX = 1, KIND_WARP_SMOOTH = 2, KIND_COMPOSE = 3 };
 
 // In-plane tile and n0 chunking of one launch of kernel `kind` over a volume
-// of shape s (tu overrides the automatic choice).
-Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu = Tuning());
+// of shape s (tu overrides the automatic choice).  cube_ok: a brick launch
+// exists for the kernel's radius and epilogue (smoothing and composition
+// kinds only).
+Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu = Tuning(), bool cube_ok = false);
 
 }  // namespace fa
 

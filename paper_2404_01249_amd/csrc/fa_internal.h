@@ -25,12 +25,17 @@ struct Ctl {
 
 // Tile geometry of one streaming launch: in-plane tile (TY x TX) along
 // (n1, n2); the workgroup marches along n0 over a chunk of ZC planes.
+// cube: the smoothing and composition kernels take whole TZ x TY x TX bricks
+// (zc = TZ planes) and run their three passes in LDS instead of marching
+// along n0 (small volumes, where the march's sequential plane steps dominate).
 struct Tiling {
   int ty, tx, zc;
   int tiles_y, tiles_x, chunks;
   int variant = 0;   // gradient kernel: 2 = gathers issued after the LDS passes
+  bool cube = false;
   int blocks() const { return tiles_y * tiles_x * chunks; }
 };
+constexpr int kCubeZ = 4, kCubeY = 8, kCubeX = 16;   // brick of a cube launch
 
 // ---- fused gradient (+ Adam) kernel -------------------------------------
 struct GradArgs {
@@ -107,6 +112,8 @@ constexpr int kMeanBlocks = 256;
 
 bool grad_tile_supported(int ty, int tx);
 bool gauss_tile_supported(int ty, int tx);
+// Whether a brick (cube) launch exists for this radius and epilogue.
+bool gauss_cube_supported(int radius, int epilogue);
 size_t grad_lds_bytes(int window, int ty, int tx);
 size_t gauss_lds_bytes(int radius, int ty, int tx);
 

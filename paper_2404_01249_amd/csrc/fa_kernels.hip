@@ -1069,6 +1069,180 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Brick forms of the smoothing and composition kernels for small volumes.
+// A workgroup takes a TZ x TY x TX brick, loads its clamped halo region into
+// LDS and runs the three separable passes there (x, then y, then z, the
+// order and summation of k_gauss, so the results are bitwise those of the
+// streaming form).  With no march along n0, a launch is a few dependent
+// steps long instead of one step per plane of a chunk plus its halo.
+// ---------------------------------------------------------------------------
+template <int R, int TZ, int TY, int TX, int EPI>
+__global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube(const GaussArgs A) {
+  constexpr int L = 2 * R + 1;
+  constexpr int NT = TZ * TY * TX;
+  constexpr int RZ = TZ + 2 * R, RY = TY + 2 * R, RX = TX + 2 * R;
+  constexpr int NR = RZ * RY * RX;   // halo region
+  constexpr int NX = RZ * RY * TX;   // after the x-pass
+  constexpr int NY = RZ * TY * TX;   // after the y-pass
+  static_assert(NY <= NR, "y-pass output reuses the region buffer");
+  extern __shared__ float lds[];
+  float* reg = lds;            // [3][NR], later [3][NY]
+  float* xo = lds + 3 * NR;    // [3][NX]
+  __shared__ double red[NT / 64];
+  __shared__ int is_last;
+
+  const int tid = threadIdx.x;
+  int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = b % A.tiles_x;
+  b /= A.tiles_x;
+  const int by = b % A.tiles_y;
+  b /= A.tiles_y;
+  const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
+  const int N = n0 * n1 * n2;
+  const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
+
+  float w[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) w[k] = A.wts[k];
+
+  for (int c = tid; c < NR; c += NT) {
+    const int zz = c / (RY * RX), r = c - zz * (RY * RX);
+    const int yy = r / RX, xx = r - yy * RX;
+    const int gz = min(max(z0 - R + zz, 0), n0 - 1);
+    const int gy = min(max(y0 - R + yy, 0), n1 - 1);
+    const int gx = min(max(x0 - R + xx, 0), n2 - 1);
+    const int idx = (gz * n1 + gy) * n2 + gx;
+    reg[c] = A.in[idx];
+    reg[NR + c] = A.in[N + idx];
+    reg[2 * NR + c] = A.in[2 * N + idx];
+  }
+  __syncthreads();
+  for (int c = tid; c < NX; c += NT) {
+    const int row = c / TX, xx = c - row * TX;
+    const float* src = reg + row * RX + xx;
+    float s0 = w[0] * src[0], s1 = w[0] * src[NR], s2 = w[0] * src[2 * NR];
+#pragma unroll
+    for (int k = 1; k < L; ++k) {
+      s0 += w[k] * src[k];
+      s1 += w[k] * src[NR + k];
+      s2 += w[k] * src[2 * NR + k];
+    }
+    xo[c] = s0;
+    xo[NX + c] = s1;
+    xo[2 * NX + c] = s2;
+  }
+  __syncthreads();
+  for (int c = tid; c < NY; c += NT) {
+    const int zz = c / (TY * TX), r = c - zz * (TY * TX);
+    const int yy = r / TX, xx = r - yy * TX;
+    const float* src = xo + (zz * RY + yy) * TX + xx;
+    float s0 = w[0] * src[0], s1 = w[0] * src[NX], s2 = w[0] * src[2 * NX];
+#pragma unroll
+    for (int k = 1; k < L; ++k) {
+      s0 += w[k] * src[k * TX];
+      s1 += w[k] * src[NX + k * TX];
+      s2 += w[k] * src[2 * NX + k * TX];
+    }
+    reg[c] = s0;
+    reg[NY + c] = s1;
+    reg[2 * NY + c] = s2;
+  }
+  __syncthreads();
+  const int tz = tid / (TY * TX), r = tid - tz * (TY * TX);
+  const int ty = r / TX, tx = r - ty * TX;
+  const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+  float mx = 0.0f;
+  if (gz < n0 && gy < n1 && gx < n2) {
+    const float* src = reg + (tz * TY + ty) * TX + tx;
+    float v0 = w[0] * src[0], v1 = w[0] * src[NY], v2 = w[0] * src[2 * NY];
+#pragma unroll
+    for (int j = 1; j < L; ++j) {
+      v0 += w[j] * src[j * TY * TX];
+      v1 += w[j] * src[NY + j * TY * TX];
+      v2 += w[j] * src[2 * NY + j * TY * TX];
+    }
+    const int idx = vidx(gz, gy, gx, n1, n2);
+    A.out[idx] = v0;
+    A.out[N + idx] = v1;
+    A.out[2 * N + idx] = v2;
+    if (EPI == EPI_SMOOTH_MAX) mx = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+  }
+  if (EPI == EPI_SMOOTH_MAX) {
+    const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
+    if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
+  }
+  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last);
+}
+
+// d' = u + d(x + u), u = -eta s / (2M), |u| <= 1 voxel, on a brick: d is
+// staged in LDS on the brick plus one voxel (zero off the grid).  Runs in
+// place over s: each thread reads s only at the voxel it writes.
+template <int TZ, int TY, int TX>
+__global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube(const GaussArgs A) {
+  constexpr int NT = TZ * TY * TX;
+  constexpr int DZ = TZ + 2, DY = TY + 2, DX = TX + 2, DE = DZ * DY * DX;
+  extern __shared__ float lds[];   // [3][DE]
+  const int tid = threadIdx.x;
+  int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = b % A.tiles_x;
+  b /= A.tiles_x;
+  const int by = b % A.tiles_y;
+  b /= A.tiles_y;
+  const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
+  const int N = n0 * n1 * n2;
+  const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
+  for (int c = tid; c < DE; c += NT) {
+    const int zz = c / (DY * DX), r = c - zz * (DY * DX);
+    const int yy = r / DX, xx = r - yy * DX;
+    const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+    const bool ok = gz >= 0 && gz < n0 && gy >= 0 && gy < n1 && gx >= 0 && gx < n2;
+    const int idx = ok ? (gz * n1 + gy) * n2 + gx : 0;
+    lds[c] = ok ? A.d[idx] : 0.0f;
+    lds[DE + c] = ok ? A.d[N + idx] : 0.0f;
+    lds[2 * DE + c] = ok ? A.d[2 * N + idx] : 0.0f;
+  }
+  const float M = __uint_as_float(A.ctl->mbits);
+  const float scale = M > 0.0f ? -A.eta / (2.0f * M) : 0.0f;
+  const int tz = tid / (TY * TX), r = tid - tz * (TY * TX);
+  const int ty = r / TX, tx = r - ty * TX;
+  const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+  const bool own = gz < n0 && gy < n1 && gx < n2;
+  const int idx = own ? vidx(gz, gy, gx, n1, n2) : 0;
+  float sv[3] = {0.f, 0.f, 0.f};
+  if (own) {
+    sv[0] = A.in[idx];
+    sv[1] = A.in[N + idx];
+    sv[2] = A.in[2 * N + idx];
+  }
+  __syncthreads();
+  if (own) {
+    // the arithmetic of k_gauss<0, EPI_COMPOSE_LDS>: floor(u) is -1 or 0
+    const float u0 = scale * sv[0], u1 = scale * sv[1], u2 = scale * sv[2];
+    const float f0 = fminf(fmaxf(floorf(u0), -1.0f), 0.0f);
+    const float f1 = fminf(fmaxf(floorf(u1), -1.0f), 0.0f);
+    const float f2 = fminf(fmaxf(floorf(u2), -1.0f), 0.0f);
+    const float t0 = u0 - f0, t1 = u1 - f1, t2 = u2 - f2;
+    const int cb = ((tz + 1 + (int)f0) * DY + (ty + 1 + (int)f1)) * DX + (tx + 1 + (int)f2);
+    float res[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float* pa = lds + q * DE + cb;
+      const float* pb = pa + DY * DX;
+      const float e00 = pa[0] + t2 * (pa[1] - pa[0]);
+      const float e01 = pa[DX] + t2 * (pa[DX + 1] - pa[DX]);
+      const float e10 = pb[0] + t2 * (pb[1] - pb[0]);
+      const float e11 = pb[DX] + t2 * (pb[DX + 1] - pb[DX]);
+      const float g0 = e00 + t1 * (e01 - e00);
+      const float g1 = e10 + t1 * (e11 - e10);
+      res[q] = g0 + t0 * (g1 - g0);
+    }
+    A.out[idx] = u0 + res[0];
+    A.out[N + idx] = u1 + res[1];
+    A.out[2 * N + idx] = u2 + res[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Off-loop kernels: pyramid blur and resampling, warp, fills, layout copies.
 // ---------------------------------------------------------------------------
 // Copy of a volume with a zero border of kPad voxels on every side.
@@ -1264,9 +1438,46 @@ hipError_t gauss_launch_tile(const GaussArgs& a, int radius, int epi, const Tili
   }
 }
 
+template <int R>
+hipError_t gauss_cube_r(const GaussArgs& a, int epi, const Tiling& t, hipStream_t s) {
+  constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
+  constexpr size_t sh = sizeof(float) * 3 *
+                        ((TZ + 2 * R) * (TY + 2 * R) * (TX + 2 * R) + (TZ + 2 * R) * (TY + 2 * R) * TX);
+  static_assert(sh <= 65536, "brick smoothing LDS exceeds 64 KiB");
+  const dim3 g(t.blocks()), blk(TZ * TY * TX);
+  switch (epi) {
+    case EPI_SMOOTH_MAX: k_gauss_cube<R, TZ, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(a); break;
+    case EPI_STORE_FINAL: k_gauss_cube<R, TZ, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gauss_launch_cube(const GaussArgs& a, int radius, int epi, const Tiling& t, hipStream_t s) {
+  if (epi == EPI_COMPOSE_LDS) {
+    if (radius != 0) return hipErrorInvalidValue;
+    constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
+    constexpr size_t sh = sizeof(float) * 3 * (TZ + 2) * (TY + 2) * (TX + 2);
+    k_compose_cube<TZ, TY, TX><<<dim3(t.blocks()), dim3(TZ * TY * TX), sh, s>>>(a);
+    return hipGetLastError();
+  }
+  switch (radius) {
+    case 0: return gauss_cube_r<0>(a, epi, t, s);
+    case 1: return gauss_cube_r<1>(a, epi, t, s);
+    case 2: return gauss_cube_r<2>(a, epi, t, s);
+    case 3: return gauss_cube_r<3>(a, epi, t, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 bool grad_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
+bool gauss_cube_supported(int radius, int epilogue) {
+  if (epilogue == EPI_COMPOSE_LDS) return radius == 0;
+  return (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE_FINAL) && radius >= 0 && radius <= 3;
+}
+
 bool gauss_tile_supported(int ty, int tx) {
   return (ty == 16 && tx == 32) || (ty == 8 && tx == 32) || (ty == 8 && tx == 64);
 }
@@ -1291,6 +1502,7 @@ hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream
 }
 
 hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
+  if (t.cube) return gauss_launch_cube(a, radius, epilogue, t, s);
   if (t.ty == 16 && t.tx == 32) return gauss_launch_tile<16, 32>(a, radius, epilogue, t, s);
   if (t.ty == 8 && t.tx == 32) return gauss_launch_tile<8, 32>(a, radius, epilogue, t, s);
   if (t.ty == 8 && t.tx == 64) return gauss_launch_tile<8, 64>(a, radius, epilogue, t, s);

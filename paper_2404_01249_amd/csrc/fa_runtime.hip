@@ -362,9 +362,31 @@ fa_status check_shape(const fa_shape& s) {
 // the two smoothing kernels make chunks below 4 planes wasteful.  (Measured
 // on the 160x192x224 pyramid: each level's time over chunks of 1 to 40
 // planes.)
-Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu) {
+Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu, bool cube_ok) {
   static const int kSlots[4] = {512, 1024, 512, 512};
   static const int kMinChunk[4] = {1, 4, 4, 1};
+  // Small volumes take bricks for the sigma_grad smoothing and the
+  // composition: there a launch is bound by the length of its chain of
+  // dependent steps, not by throughput.  (Measured at 40x48x56: 15.8 -> 11.5
+  // and 7.2 -> 6.7 us.  The warp smoothing, which also ends the iteration,
+  // was slower as a brick there, 17.1 -> 21.3 us, and at 80x96x112 every
+  // brick form lost to the march.)  Tuning variant: 1 forces the march,
+  // 2 the bricks.
+  constexpr int64_t kCubeMaxVoxels = 300000;
+  const bool cube_auto = kind == KIND_SMOOTH_MAX || kind == KIND_COMPOSE;
+  const bool cube = cube_ok && kind != KIND_GRAD &&
+                    (tu.variant == 2 || (tu.variant == 0 && cube_auto && voxels(s) <= kCubeMaxVoxels));
+  if (cube) {
+    Tiling t;
+    t.cube = true;
+    t.ty = kCubeY;
+    t.tx = kCubeX;
+    t.zc = kCubeZ;
+    t.tiles_y = (s.n1 + kCubeY - 1) / kCubeY;
+    t.tiles_x = (s.n2 + kCubeX - 1) / kCubeX;
+    t.chunks = (s.n0 + kCubeZ - 1) / kCubeZ;
+    return t;
+  }
   Tiling t;
   t.tx = 32;
   t.ty = s.n1 >= 16 ? 16 : 8;
@@ -460,9 +482,12 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     if (lv[i].shape.n0 < 2 || lv[i].shape.n1 < 2 || lv[i].shape.n2 < 2)
       return fail(FA_ESHAPE, "level " + std::to_string(i) + " has a dimension < 2");
     lv[i].tg = choose_tiling(lv[i].shape, fa::KIND_GRAD, P->tune[0]);
-    lv[i].tsg = choose_tiling(lv[i].shape, fa::KIND_SMOOTH_MAX, P->tune[1]);
-    lv[i].tsw = choose_tiling(lv[i].shape, fa::KIND_WARP_SMOOTH, P->tune[2]);
-    lv[i].tsc = choose_tiling(lv[i].shape, fa::KIND_COMPOSE, P->tune[3]);
+    lv[i].tsg = choose_tiling(lv[i].shape, fa::KIND_SMOOTH_MAX, P->tune[1],
+                              fa::gauss_cube_supported(P->rg, fa::EPI_SMOOTH_MAX));
+    lv[i].tsw = choose_tiling(lv[i].shape, fa::KIND_WARP_SMOOTH, P->tune[2],
+                              fa::gauss_cube_supported(P->rw, fa::EPI_STORE_FINAL));
+    lv[i].tsc = choose_tiling(lv[i].shape, fa::KIND_COMPOSE, P->tune[3],
+                              P->p.eta <= 2.0f && fa::gauss_cube_supported(0, fa::EPI_COMPOSE_LDS));
     total_iters += iters[i];
     nmax = std::max(nmax, lv[i].n);
     pmax = std::max(pmax, lv[i].tg.blocks());

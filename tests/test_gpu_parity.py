@@ -142,6 +142,26 @@ def test_one_iteration_step_variants(eta, sigma_grad, sigma_warp):
     pr.close()
 
 
+@pytest.mark.parametrize("shape,sigma_grad,sigma_warp,eta", [((21, 37, 45), 1.0, 0.5, 0.5), ((40, 48, 56), 0.3, 0.0, 2.0),
+                                                           ((7, 5, 6), 0.0, 1.0, 1.0), ((13, 17, 33), 0.9, 0.9, 0.25)])
+def test_brick_launches_match_streaming_launches(shape, sigma_grad, sigma_warp, eta):
+    """The brick (whole-in-LDS) forms of the smoothing and composition kernels
+    give bitwise the results of the streaming forms (radii 0 to 3)."""
+    fixed, moving, _ = make_problem(shape, seed=36)
+    out = []
+    for variant in (1, 2):
+        pr = new_pair(fixed, moving, eta=eta, sigma_grad=sigma_grad, sigma_warp=sigma_warp, window=5)
+        for kind in (1, 2, 3):
+            fa.fa_pair_set_tuning(pr.handle, kind, 0, 0, 0, variant)
+        pr.set_schedule([1.0], [6])
+        pr.run()
+        out.append((pr.loss_history(), host(pr.field()), pr.step_norm()))
+        pr.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+
+
 def test_first_iteration_moves_at_most_eta_over_two():
     fixed, moving, _ = make_problem((21, 37, 45), seed=41)
     pr = new_pair(fixed, moving, eta=0.5, sigma_grad=1.0, sigma_warp=0.0)
