@@ -65,11 +65,12 @@ fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_m
  * 2 = the sigma_warp smoothing kernel, 3 = the composition kernel.  ty x tx
  * is the in-plane tile (n1 x n2): 16x32 or 8x32 for every kind, 8x64 also for
  * kinds 1 to 3, or 0x0 for the automatic choice; zc is the number of n0 planes
- * per workgroup (0 = automatic).  variant, kind 0: the gradient kernel's
- * schedule (0 automatic, 1 next-plane gathers overlapped with the LDS passes,
- * 2 issued after them); kinds 1 to 3: 0 automatic (for kinds 1 and 3,
- * volumes of at most 300,000 voxels take 4x8x16 bricks processed whole in
- * LDS), 1 the streaming form, 2 bricks where supported.
+ * per workgroup (0 = automatic).  Volumes of at most 300,000 voxels take
+ * 4x8x16 bricks processed whole in LDS instead of the march along n0, for
+ * kinds 0 (windows 1 to 5), 1 and 3.  variant, kind 0: 0 automatic, 1 the
+ * march with next-plane gathers overlapped with the LDS passes, 2 the march
+ * with them issued after the passes, 3 bricks; kinds 1 to 3: 0 automatic,
+ * 1 the march, 2 bricks where supported.
  * Takes effect at the next fa_pair_set_schedule.  Results do not depend on
  * the launch shape beyond floating-point summation order. */
 fa_status fa_pair_set_tuning(fa_pair pair, int kind, int ty, int tx, int zc, int variant);

@@ -114,6 +114,7 @@ bool grad_tile_supported(int ty, int tx);
 bool gauss_tile_supported(int ty, int tx);
 // Whether a brick (cube) launch exists for this radius and epilogue.
 bool gauss_cube_supported(int radius, int epilogue);
+bool grad_cube_supported(int window);
 size_t grad_lds_bytes(int window, int ty, int tx);
 size_t gauss_lds_bytes(int radius, int ty, int tx);
 

@@ -1069,6 +1069,240 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Brick form of the gradient kernel for small volumes.  A workgroup takes a
+// TZ x TY x TX brick: it loads I and J = I_m(x + d) on the brick plus a 2r
+// halo into LDS, forms the window sums of I, J, I^2, J^2 and IJ with three
+// separable passes (x, y, z), the per-centre coefficients A, B, C on the
+// brick plus an r halo, their window sums with three more passes, and the
+// output as in k_grad.  No plane-by-plane march: the launch is a short chain
+// of dependent steps, which is what bounds small volumes.  The sums run in a
+// different order from the streaming form (x, y, z instead of z, x, y), so
+// the two agree to rounding, not bitwise.
+// ---------------------------------------------------------------------------
+template <int W, int TZ, int TY, int TX>
+struct GradCubeShape {
+  static constexpr int R = W / 2;
+  static constexpr int QZ = TZ + 4 * R, QY = TY + 4 * R, QX = TX + 4 * R, NQ = QZ * QY * QX;  // I, J
+  static constexpr int CZ = TZ + 2 * R, CY = TY + 2 * R, CX = TX + 2 * R, NC = CZ * CY * CX;  // centres
+  static constexpr int NX1 = QZ * QY * CX;   // stage-1 sums after the x pass
+  static constexpr int NY1 = QZ * CY * CX;   // ... after the y pass
+  static constexpr int NX2 = CZ * CY * TX;   // stage-2 sums after the x pass
+  static constexpr int NY2 = CZ * TY * TX;   // ... after the y pass
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int SA = cmax(2 * NQ, cmax(5 * NY1, 3 * NX2));   // I, J -> stage-1 y -> stage-2 x
+  static constexpr int SB = cmax(5 * NX1, cmax(3 * NC, 3 * NY2));   // stage-1 x -> A, B, C -> stage-2 y
+  static constexpr size_t lds_bytes = sizeof(float) * (size_t)(SA + SB);
+};
+
+template <int W, int TZ, int TY, int TX>
+__global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
+  using S = GradCubeShape<W, TZ, TY, TX>;
+  constexpr int R = S::R;
+  constexpr int NT = TZ * TY * TX;
+  constexpr int QY = S::QY, QX = S::QX, NQ = S::NQ;
+  constexpr int CY = S::CY, CX = S::CX, NC = S::NC;
+  constexpr int NX1 = S::NX1, NY1 = S::NY1, NX2 = S::NX2, NY2 = S::NY2;
+  extern __shared__ float lds[];
+  float* bufA = lds;
+  float* bufB = lds + S::SA;
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = b % A.tiles_x;
+  b /= A.tiles_x;
+  const int by = b % A.tiles_y;
+  b /= A.tiles_y;
+  const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
+  const int N = n0 * n1 * n2;
+  const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
+  const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
+  if (A.mode == 0 && blockIdx.x == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
+
+  // the thread's own output voxel: I, J and grad_p I_m, Adam moments
+  const int tz = tid / (TY * TX), tr = tid - tz * (TY * TX);
+  const int ty = tr / TX, tx = tr - ty * TX;
+  const int oz = z0 + tz, oy = y0 + ty, ox = x0 + tx;
+  const bool own = oz < n0 && oy < n1 && ox < n2;
+  const int oidx = own ? vidx(oz, oy, ox, n1, n2) : 0;
+  float oI = 0.f, oJ = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  float pm[3] = {0.f, 0.f, 0.f}, pv[3] = {0.f, 0.f, 0.f};
+  if (own) {
+    const Cell8 c = cell8_pad(n0, n1, n2, oz, oy, ox, A.d[oidx], A.d[N + oidx], A.d[2 * N + oidx]);
+    Gather gq;
+    gather_issue(A.moving_pad, c, gq);
+    oI = A.fixed[oidx] - si;
+    if (A.mode == 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        pm[q] = A.m[q * N + oidx];
+        pv[q] = A.v[q * N + oidx];
+      }
+    }
+    oJ = gather_value_grad(gq, g0, g1, g2) - sj;
+  }
+
+  // stage-1 inputs on the brick plus 2r (zero off the grid)
+  for (int c = tid; c < NQ; c += NT) {
+    const int qz = c / (QY * QX), r = c - qz * (QY * QX);
+    const int qy = r / QX, qx = r - qy * QX;
+    const int z = z0 - 2 * R + qz, y = y0 - 2 * R + qy, x = x0 - 2 * R + qx;
+    float I = 0.f, J = 0.f;
+    if (z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2) {
+      const int idx = vidx(z, y, x, n1, n2);
+      const Cell8 c8 = cell8_pad(n0, n1, n2, z, y, x, A.d[idx], A.d[N + idx], A.d[2 * N + idx]);
+      Gather gq;
+      gather_issue(A.moving_pad, c8, gq);
+      I = A.fixed[idx] - si;
+      J = gather_value(gq) - sj;
+    }
+    bufA[c] = I;
+    bufA[NQ + c] = J;
+  }
+  __syncthreads();
+  // stage 1, x: sums of I, J, I^2, J^2, IJ over w voxels
+  for (int c = tid; c < NX1; c += NT) {
+    const int row = c / CX, xo = c - row * CX;
+    const float* pI = bufA + row * QX + xo;
+    const float* pJ = pI + NQ;
+    const float i0 = pI[0], j0 = pJ[0];
+    float s0 = i0, s1 = j0, s2 = i0 * i0, s3 = j0 * j0, s4 = i0 * j0;
+#pragma unroll
+    for (int k = 1; k < W; ++k) {
+      const float i_ = pI[k], j_ = pJ[k];
+      s0 += i_;
+      s1 += j_;
+      s2 += i_ * i_;
+      s3 += j_ * j_;
+      s4 += i_ * j_;
+    }
+    bufB[c] = s0;
+    bufB[NX1 + c] = s1;
+    bufB[2 * NX1 + c] = s2;
+    bufB[3 * NX1 + c] = s3;
+    bufB[4 * NX1 + c] = s4;
+  }
+  __syncthreads();
+  // stage 1, y
+  for (int c = tid; c < NY1; c += NT) {
+    const int zq = c / (CY * CX), r = c - zq * (CY * CX);
+    const int yo = r / CX, xo = r - yo * CX;
+    const float* src = bufB + (zq * QY + yo) * CX + xo;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const float* p = src + q * NX1;
+      float sum = p[0];
+#pragma unroll
+      for (int k = 1; k < W; ++k) sum += p[k * CX];
+      bufA[q * NY1 + c] = sum;
+    }
+  }
+  __syncthreads();
+  // stage 1, z, and the per-centre coefficients on the brick plus r
+  float lacc = 0.0f;
+  for (int c = tid; c < NC; c += NT) {
+    const int cz = c / (CY * CX), r = c - cz * (CY * CX);
+    const int cy = r / CX, cx = r - cy * CX;
+    const float* src = bufA + (cz * CY + cy) * CX + cx;
+    float St[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const float* p = src + q * NY1;
+      float sum = p[0];
+#pragma unroll
+      for (int k = 1; k < W; ++k) sum += p[k * CY * CX];
+      St[q] = sum;
+    }
+    const int z = z0 - R + cz, y = y0 - R + cy, x = x0 - R + cx;
+    const bool ok = z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2;
+    float ca = 0.f, cb = 0.f, cc_ = 0.f;
+    // a one-voxel window has zero variance and covariance: every coefficient is 0
+    if (W > 1 && ok) {
+      const float cnt = clipped_count(z, n0, R) * (clipped_count(y, n1, R) * clipped_count(x, n2, R));
+      const float icnt = __builtin_amdgcn_rcpf(cnt);
+      const float muI = St[0] * icnt, muJ = St[1] * icnt;
+      const float cross = St[4] - muI * St[1];
+      const float vI = St[2] - muI * St[0];
+      const float vJ = St[3] - muJ * St[1];
+      const float D = vI * vJ + A.eps_cc;
+      if (D != 0.0f) {
+        const float invD = __builtin_amdgcn_rcpf(D);
+        const float cc = cross * cross * invD;
+        ca = 2.0f * cross * invD;
+        cb = -2.0f * cc * vI * invD;
+        cc_ = ca * muI + cb * muJ;
+        if (cz >= R && cz < R + TZ && cy >= R && cy < R + TY && cx >= R && cx < R + TX) lacc += cc;
+      }
+    }
+    bufB[c] = ca;
+    bufB[NC + c] = cb;
+    bufB[2 * NC + c] = cc_;
+  }
+  __syncthreads();
+  // stage 2 (sums of A, B, C over the window around each brick voxel), x
+  for (int c = tid; c < NX2; c += NT) {
+    const int row = c / TX, xo = c - row * TX;
+    const float* src = bufB + row * CX + xo;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float* p = src + q * NC;
+      float sum = p[0];
+#pragma unroll
+      for (int k = 1; k < W; ++k) sum += p[k];
+      bufA[q * NX2 + c] = sum;
+    }
+  }
+  __syncthreads();
+  // stage 2, y
+  for (int c = tid; c < NY2; c += NT) {
+    const int zc = c / (TY * TX), r = c - zc * (TY * TX);
+    const int yo = r / TX, xo = r - yo * TX;
+    const float* src = bufA + (zc * CY + yo) * TX + xo;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float* p = src + q * NX2;
+      float sum = p[0];
+#pragma unroll
+      for (int k = 1; k < W; ++k) sum += p[k * TX];
+      bufB[q * NY2 + c] = sum;
+    }
+  }
+  __syncthreads();
+  // stage 2, z, and the output
+  if (own) {
+    const float* src = bufB + (tz * TY + ty) * TX + tx;
+    float SA = src[0], SB = src[NY2], SC = src[2 * NY2];
+#pragma unroll
+    for (int k = 1; k < W; ++k) {
+      SA += src[k * TY * TX];
+      SB += src[NY2 + k * TY * TX];
+      SC += src[2 * NY2 + k * TY * TX];
+    }
+    const float dl = -A.inv_n * (oI * SA + oJ * SB - SC);
+    const float g[3] = {dl * g0, dl * g1, dl * g2};
+    if (A.mode == 0) {
+      const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
+      const float b1 = A.beta1, b2 = A.beta2;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int iq = q * N + oidx;
+        const float mm = b1 * pm[q] + (1.0f - b1) * g[q];
+        const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
+        A.m[iq] = mm;
+        A.v[iq] = vv;
+        A.out[iq] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps);
+      }
+    } else if (A.mode == 1) {
+      const float gsc = A.gscale ? *A.gscale : 1.0f;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) A.out[q * N + oidx] = g[q] * gsc;
+    }
+  }
+  const double tot = block_sum<NT>((double)lacc, red);
+  if (tid == 0) A.partials[blockIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
 // Brick forms of the smoothing and composition kernels for small volumes.
 // A workgroup takes a TZ x TY x TX brick, loads its clamped halo region into
 // LDS and runs the three separable passes there (x, then y, then z, the
@@ -1470,9 +1704,36 @@ hipError_t gauss_launch_cube(const GaussArgs& a, int radius, int epi, const Tili
   }
 }
 
+template <int W>
+hipError_t grad_cube_w(const GradArgs& a, const Tiling& t, hipStream_t s) {
+  constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
+  constexpr size_t sh = GradCubeShape<W, TZ, TY, TX>::lds_bytes;
+  static_assert(sh <= 160 * 1024 - 1024, "brick gradient LDS exceeds the 160 KiB of a CU");
+  static bool attr_set = false;   // raise the dynamic LDS limit once per process
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube<W, TZ, TY, TX>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  k_grad_cube<W, TZ, TY, TX><<<dim3(t.blocks()), dim3(TZ * TY * TX), sh, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t grad_launch_cube(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
+  switch (window) {
+    case 1: return grad_cube_w<1>(a, t, s);
+    case 3: return grad_cube_w<3>(a, t, s);
+    case 5: return grad_cube_w<5>(a, t, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 bool grad_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
+bool grad_cube_supported(int window) { return window == 1 || window == 3 || window == 5; }
+
 bool gauss_cube_supported(int radius, int epilogue) {
   if (epilogue == EPI_COMPOSE_LDS) return radius == 0;
   return (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE_FINAL) && radius >= 0 && radius <= 3;
@@ -1496,6 +1757,7 @@ size_t gauss_lds_bytes(int radius, int ty, int tx) {
 }
 
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
+  if (t.cube) return grad_launch_cube(a, window, t, s);
   if (t.ty == 16 && t.tx == 32) return grad_launch_tile<16, 32>(a, window, t, s);
   if (t.ty == 8 && t.tx == 32) return grad_launch_tile<8, 32>(a, window, t, s);
   return hipErrorInvalidValue;

@@ -52,7 +52,7 @@ fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_str
   h->n = fa::voxels(shape);
   h->window = window;
   h->eps = cc_eps;
-  h->tg = fa::choose_tiling(shape, fa::KIND_GRAD);
+  h->tg = fa::choose_tiling(shape, fa::KIND_GRAD, fa::Tuning(), fa::grad_cube_supported(window));
   const int nb = h->tg.blocks();
   if (hipMalloc((void**)&h->ctl, sizeof(fa::Ctl)) != hipSuccess ||
       hipMalloc((void**)&h->partials, (size_t)nb * sizeof(double)) != hipSuccess ||

@@ -372,10 +372,12 @@ Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu, bool 
   // was slower as a brick there, 17.1 -> 21.3 us, and at 80x96x112 every
   // brick form lost to the march.)  Tuning variant: 1 forces the march,
   // 2 the bricks.
+  // The gradient kernel's brick form (tuning variant 3) is chosen likewise.
   constexpr int64_t kCubeMaxVoxels = 300000;
-  const bool cube_auto = kind == KIND_SMOOTH_MAX || kind == KIND_COMPOSE;
-  const bool cube = cube_ok && kind != KIND_GRAD &&
-                    (tu.variant == 2 || (tu.variant == 0 && cube_auto && voxels(s) <= kCubeMaxVoxels));
+  const bool cube_auto = kind != KIND_WARP_SMOOTH;
+  const int cube_variant = kind == KIND_GRAD ? 3 : 2;
+  const bool cube = cube_ok && (tu.variant == cube_variant ||
+                                (tu.variant == 0 && cube_auto && voxels(s) <= kCubeMaxVoxels));
   if (cube) {
     Tiling t;
     t.cube = true;
@@ -481,7 +483,7 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     lv[i].n = voxels(lv[i].shape);
     if (lv[i].shape.n0 < 2 || lv[i].shape.n1 < 2 || lv[i].shape.n2 < 2)
       return fail(FA_ESHAPE, "level " + std::to_string(i) + " has a dimension < 2");
-    lv[i].tg = choose_tiling(lv[i].shape, fa::KIND_GRAD, P->tune[0]);
+    lv[i].tg = choose_tiling(lv[i].shape, fa::KIND_GRAD, P->tune[0], fa::grad_cube_supported(P->p.cc_window));
     lv[i].tsg = choose_tiling(lv[i].shape, fa::KIND_SMOOTH_MAX, P->tune[1],
                               fa::gauss_cube_supported(P->rg, fa::EPI_SMOOTH_MAX));
     lv[i].tsw = choose_tiling(lv[i].shape, fa::KIND_WARP_SMOOTH, P->tune[2],
@@ -763,7 +765,8 @@ fa_status fa_pair_set_tuning(fa_pair P, int kind, int ty, int tx, int zc, int va
   const bool autotile = ty == 0 && tx == 0;
   if (!autotile && !(kind == 0 ? fa::grad_tile_supported(ty, tx) : fa::gauss_tile_supported(ty, tx)))
     return fail(FA_EINVAL, "unsupported tile shape");
-  if (zc < 0 || variant < 0 || variant > 2) return fail(FA_EINVAL, "zc must be >= 0 and variant in [0, 2]");
+  if (zc < 0 || variant < 0 || variant > (kind == 0 ? 3 : 2))
+    return fail(FA_EINVAL, "zc must be >= 0 and variant in [0, 3] (kind 0) or [0, 2] (kinds 1 to 3)");
   P->tune[kind].ty = ty;
   P->tune[kind].tx = tx;
   P->tune[kind].zc = zc;

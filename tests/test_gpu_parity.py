@@ -78,11 +78,18 @@ def test_warp_identity_shift_and_random(shape):
     pr.close()
 
 
+# gradient kernel forms: 1 = the march along n0, 3 = bricks (windows 1 to 5;
+# the automatic choice for volumes up to 300,000 voxels)
+GRAD_FORMS = [1, 3]
+
+
+@pytest.mark.parametrize("form", GRAD_FORMS)
 @pytest.mark.parametrize("window", [1, 3, 5, 7, 9])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_gradient_and_loss_match_oracle(shape, window):
+def test_gradient_and_loss_match_oracle(shape, window, form):
     fixed, moving, d = make_problem(shape, seed=21 + window)
     pr = new_pair(fixed, moving, window=window)
+    fa.fa_pair_set_tuning(pr.handle, 0, 0, 0, 0, form)
     pr.set_schedule([1.0], [1])
     pr.set_state(dev(d), None, None, 0)
     g, loss = pr.eval_gradient()
@@ -92,8 +99,9 @@ def test_gradient_and_loss_match_oracle(shape, window):
     pr.close()
 
 
+@pytest.mark.parametrize("form", GRAD_FORMS)
 @pytest.mark.parametrize("shape", [(21, 37, 45), (12, 131, 133)])
-def test_one_iteration_from_injected_state(shape):
+def test_one_iteration_from_injected_state(shape, form):
     """Every intermediate of one iteration of Algorithm 1 from the same state."""
     fixed, moving, d = make_problem(shape, seed=31)
     rng = np.random.default_rng(32)
@@ -102,6 +110,7 @@ def test_one_iteration_from_injected_state(shape):
     t_done = 7
     P = O.Params(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5)
     pr = new_pair(fixed, moving, eta=P.eta, sigma_grad=P.sigma_grad, sigma_warp=P.sigma_warp, window=5)
+    fa.fa_pair_set_tuning(pr.handle, 0, 0, 0, 0, form)
     pr.set_schedule([1.0], [1])
     pr.set_state(dev(d), dev(m), dev(v), t_done)
     pr.step(1)
@@ -208,23 +217,28 @@ def test_level_transition_upsamples_state():
     pr.close()
 
 
-def _full_run(name):
+def _full_run(name, form=0):
     p = synth.load(name)
     gold = np.load(os.path.join(HERE, "golden", f"{name}_oracle.npz"), allow_pickle=False)
     pr = new_pair(p.fixed, p.moving, eta=float(gold["eta"]), sigma_grad=float(gold["sigma_grad"]),
                   sigma_warp=float(gold["sigma_warp"]), window=int(gold["window"]))
+    for kind in range(4):
+        fa.fa_pair_set_tuning(pr.handle, kind, 0, 0, 0, form)
     pr.set_schedule(list(gold["scales"]), [int(i) for i in gold["iters"]])
     done = pr.run()
     assert done == int(np.sum(gold["iters"]))
     return p, gold, pr
 
 
-def test_full_run_blobs64_matches_oracle():
-    """Whole 64^3 two-level run against the stored oracle run.  The bound is
-    the mean endpoint difference (0.05 voxel); the loss trajectory is also
-    held close (fp32 and fp64 trajectories separate slowly once the
-    fixed-length steps of Appendix E oscillate around the optimum)."""
-    p, gold, pr = _full_run("blobs64")
+@pytest.mark.parametrize("form", [0, 1])
+def test_full_run_blobs64_matches_oracle(form):
+    """Whole 64^3 two-level run against the stored oracle run, with the
+    automatic kernel forms (bricks at both levels) and with every kernel
+    marching along n0.  The bound is the mean endpoint difference (0.05
+    voxel); the loss trajectory is also held close (fp32 and fp64
+    trajectories separate slowly once the fixed-length steps of Appendix E
+    oscillate around the optimum)."""
+    p, gold, pr = _full_run("blobs64", form)
     loss = pr.loss_history().astype(np.float64)
     ref = gold["losses"]
     assert loss.shape == ref.shape
