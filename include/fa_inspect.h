@@ -66,8 +66,8 @@ fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_m
  * is the in-plane tile (n1 x n2): 16x32 or 8x32 for every kind, 8x64 also for
  * kinds 1 to 3, or 0x0 for the automatic choice; zc is the number of n0 planes
  * per workgroup (0 = automatic).  Volumes of at most 300,000 voxels take
- * 4x8x16 bricks processed whole in LDS instead of the march along n0, for
- * kinds 0 (windows 1 to 5), 1 and 3.  variant, kind 0: 0 automatic, 1 the
+ * 4x8x16 bricks processed whole in LDS instead of the march along n0
+ * (kind 0: windows 1 to 5; kinds 1 and 2: radii up to 3).  variant, kind 0: 0 automatic, 1 the
  * march with next-plane gathers overlapped with the LDS passes, 2 the march
  * with them issued after the passes, 3 bricks; kinds 1 to 3: 0 automatic,
  * 1 the march, 2 bricks where supported.

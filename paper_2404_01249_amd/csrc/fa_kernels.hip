@@ -777,20 +777,20 @@ __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)
 // ---------------------------------------------------------------------------
 // End of an iteration, in the last launch: the last workgroup to finish
 // records the iteration's loss from the gradient kernel's partials and
-// advances the Adam step count.  No workgroup of the launch reads the control
-// block, so the update cannot race.
+// advances the Adam step count.  Everything it reads was written by earlier
+// launches, and no workgroup of this launch reads what it writes, so the
+// completion count needs no memory fences: only the atomic itself, which
+// hands the epilogue to exactly one workgroup.
 template <int NT>
 __device__ __forceinline__ void finish_iteration(const GaussArgs& A, double* red, int* is_last) {
   const int tid = threadIdx.x;
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
     const unsigned prev = atomicAdd(&A.ctl->ticket, 1u);
     *is_last = (prev == gridDim.x - 1) ? 1 : 0;
   }
   __syncthreads();
   if (*is_last) {
-    __threadfence();
     double s = 0.0;
     for (int i = tid; i < A.n_partials; i += NT) s += A.partials[i];
     s = block_sum<NT>(s, red);

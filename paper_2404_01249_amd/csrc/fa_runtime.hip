@@ -365,19 +365,16 @@ fa_status check_shape(const fa_shape& s) {
 Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu, bool cube_ok) {
   static const int kSlots[4] = {512, 1024, 512, 512};
   static const int kMinChunk[4] = {1, 4, 4, 1};
-  // Small volumes take bricks for the sigma_grad smoothing and the
-  // composition: there a launch is bound by the length of its chain of
-  // dependent steps, not by throughput.  (Measured at 40x48x56: 15.8 -> 11.5
-  // and 7.2 -> 6.7 us.  The warp smoothing, which also ends the iteration,
-  // was slower as a brick there, 17.1 -> 21.3 us, and at 80x96x112 every
-  // brick form lost to the march.)  Tuning variant: 1 forces the march,
-  // 2 the bricks.
-  // The gradient kernel's brick form (tuning variant 3) is chosen likewise.
+  // Small volumes take bricks: there a launch is bound by the length of its
+  // chain of dependent steps, not by throughput.  (Measured at 40x48x56:
+  // gradient 34.3 -> 22.5 us, sigma_grad smoothing 16.0 -> 11.9, composition
+  // 7.3 -> 6.7, warp smoothing 14.0 -> 11.7; at 80x96x112 every brick form
+  // loses to the march.)  Tuning variant: 1 forces the march, 2 (kinds 1 to
+  // 3) or 3 (kind 0) the bricks.
   constexpr int64_t kCubeMaxVoxels = 300000;
-  const bool cube_auto = kind != KIND_WARP_SMOOTH;
   const int cube_variant = kind == KIND_GRAD ? 3 : 2;
   const bool cube = cube_ok && (tu.variant == cube_variant ||
-                                (tu.variant == 0 && cube_auto && voxels(s) <= kCubeMaxVoxels));
+                                (tu.variant == 0 && voxels(s) <= kCubeMaxVoxels));
   if (cube) {
     Tiling t;
     t.cube = true;
