@@ -1142,22 +1142,47 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
     oJ = gather_value_grad(gq, g0, g1, g2) - sj;
   }
 
-  // stage-1 inputs on the brick plus 2r (zero off the grid)
-  for (int c = tid; c < NQ; c += NT) {
-    const int qz = c / (QY * QX), r = c - qz * (QY * QX);
-    const int qy = r / QX, qx = r - qy * QX;
-    const int z = z0 - 2 * R + qz, y = y0 - 2 * R + qy, x = x0 - 2 * R + qx;
-    float I = 0.f, J = 0.f;
-    if (z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2) {
-      const int idx = vidx(z, y, x, n1, n2);
-      const Cell8 c8 = cell8_pad(n0, n1, n2, z, y, x, A.d[idx], A.d[N + idx], A.d[2 * N + idx]);
-      Gather gq;
-      gather_issue(A.moving_pad, c8, gq);
-      I = A.fixed[idx] - si;
-      J = gather_value(gq) - sj;
+  // stage-1 inputs on the brick plus 2r (zero off the grid), in batches of
+  // KB voxels per thread: the batch's loads of d, then its gathers, are all
+  // in flight together instead of one voxel's dependent loads at a time
+  constexpr int KQ = (NQ + NT - 1) / NT;   // voxels per thread
+  constexpr int KB = 3;                    // batch
+#pragma unroll 1
+  for (int k0 = 0; k0 < KQ; k0 += KB) {
+    int qidx[KB];
+    bool qok[KB];
+    float qd0[KB], qd1[KB], qd2[KB], qf[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int c = tid + (k0 + j) * NT;
+      const int qz = c / (QY * QX), r = c - qz * (QY * QX);
+      const int qy = r / QX, qx = r - qy * QX;
+      const int z = z0 - 2 * R + qz, y = y0 - 2 * R + qy, x = x0 - 2 * R + qx;
+      qok[j] = k0 + j < KQ && c < NQ && z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2;
+      qidx[j] = qok[j] ? vidx(z, y, x, n1, n2) : 0;
+      qd0[j] = qok[j] ? A.d[qidx[j]] : 0.0f;
+      qd1[j] = qok[j] ? A.d[N + qidx[j]] : 0.0f;
+      qd2[j] = qok[j] ? A.d[2 * N + qidx[j]] : 0.0f;
+      qf[j] = qok[j] ? A.fixed[qidx[j]] : 0.0f;
     }
-    bufA[c] = I;
-    bufA[NQ + c] = J;
+    Gather gq[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int c = tid + (k0 + j) * NT;
+      const int qz = c / (QY * QX), r = c - qz * (QY * QX);
+      const int qy = r / QX, qx = r - qy * QX;
+      const Cell8 c8 = cell8_pad(n0, n1, n2, z0 - 2 * R + qz, y0 - 2 * R + qy, x0 - 2 * R + qx,
+                                 qd0[j], qd1[j], qd2[j]);
+      gather_issue(A.moving_pad, c8, gq[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int c = tid + (k0 + j) * NT;
+      if (k0 + j < KQ && c < NQ) {
+        bufA[c] = qok[j] ? qf[j] - si : 0.0f;
+        bufA[NQ + c] = qok[j] ? gather_value(gq[j]) - sj : 0.0f;
+      }
+    }
   }
   __syncthreads();
   // stage 1, x: sums of I, J, I^2, J^2, IJ over w voxels
@@ -1339,16 +1364,30 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube(const GaussArgs A) 
 #pragma unroll
   for (int k = 0; k < L; ++k) w[k] = A.wts[k];
 
-  for (int c = tid; c < NR; c += NT) {
+  // the region's loads are all issued before any is consumed
+  constexpr int KR = (NR + NT - 1) / NT;
+  float rv[KR][3];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int c = min(tid + k * NT, NR - 1);
     const int zz = c / (RY * RX), r = c - zz * (RY * RX);
     const int yy = r / RX, xx = r - yy * RX;
     const int gz = min(max(z0 - R + zz, 0), n0 - 1);
     const int gy = min(max(y0 - R + yy, 0), n1 - 1);
     const int gx = min(max(x0 - R + xx, 0), n2 - 1);
     const int idx = (gz * n1 + gy) * n2 + gx;
-    reg[c] = A.in[idx];
-    reg[NR + c] = A.in[N + idx];
-    reg[2 * NR + c] = A.in[2 * N + idx];
+    rv[k][0] = A.in[idx];
+    rv[k][1] = A.in[N + idx];
+    rv[k][2] = A.in[2 * N + idx];
+  }
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int c = tid + k * NT;
+    if (c < NR) {
+      reg[c] = rv[k][0];
+      reg[NR + c] = rv[k][1];
+      reg[2 * NR + c] = rv[k][2];
+    }
   }
   __syncthreads();
   for (int c = tid; c < NX; c += NT) {
@@ -1425,15 +1464,28 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube(const GaussArgs A
   const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
   const int N = n0 * n1 * n2;
   const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
-  for (int c = tid; c < DE; c += NT) {
+  constexpr int KD = (DE + NT - 1) / NT;
+  float dv[KD][3];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const int c = tid + k * NT;
     const int zz = c / (DY * DX), r = c - zz * (DY * DX);
     const int yy = r / DX, xx = r - yy * DX;
     const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
-    const bool ok = gz >= 0 && gz < n0 && gy >= 0 && gy < n1 && gx >= 0 && gx < n2;
+    const bool ok = c < DE && gz >= 0 && gz < n0 && gy >= 0 && gy < n1 && gx >= 0 && gx < n2;
     const int idx = ok ? (gz * n1 + gy) * n2 + gx : 0;
-    lds[c] = ok ? A.d[idx] : 0.0f;
-    lds[DE + c] = ok ? A.d[N + idx] : 0.0f;
-    lds[2 * DE + c] = ok ? A.d[2 * N + idx] : 0.0f;
+    dv[k][0] = ok ? A.d[idx] : 0.0f;
+    dv[k][1] = ok ? A.d[N + idx] : 0.0f;
+    dv[k][2] = ok ? A.d[2 * N + idx] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const int c = tid + k * NT;
+    if (c < DE) {
+      lds[c] = dv[k][0];
+      lds[DE + c] = dv[k][1];
+      lds[2 * DE + c] = dv[k][2];
+    }
   }
   const float M = __uint_as_float(A.ctl->mbits);
   const float scale = M > 0.0f ? -A.eta / (2.0f * M) : 0.0f;
