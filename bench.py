@@ -15,6 +15,9 @@ Prints one JSON line.  Besides the headline value it reports
   the 8 TB/s HBM peak;
 * ``plain_torch``: the same algorithm written with stock PyTorch operators
   (grid_sample, conv3d, autograd, elementwise Adam) on the same GPU;
+* ``use_jac``: the same registration with Algorithm 1's use_jac on (the
+  Eulerian direction J(phi)^T dU/dphi), its time relative to the default
+  Jacobian-free form, and its accuracy;
 * ``accuracy``: Dice of the transferred tissue labels and the fraction of
   singular voxels for the fused result and the plain PyTorch result (the
   "same accuracy" condition of the comparison);
@@ -113,6 +116,32 @@ def run_fused(p, steps, warmup, params, prof_steps=2):
     return ms, wall / steps, prof, loss, field
 
 
+def run_use_jac(p, steps, params):
+    """Whole registrations with Algorithm 1's use_jac on (Eulerian descent,
+    Section 4.4.2): milliseconds per registration and the final loss."""
+    import torch
+
+    from paper_2404_01249_amd import Pair
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    stream = torch.cuda.current_stream()
+    pr = Pair(fixed, moving, stream=stream, use_jac=True, **params)
+    pr.set_schedule(p.scales, p.iters)
+    pr.run()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        pr.set_schedule(p.scales, p.iters)
+        pr.run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    loss = pr.loss_history()
+    field = pr.field()
+    pr.close()
+    return start.elapsed_time(end) / steps, float(loss[-1]), field
+
+
 def run_plain(p, steps, warmup, params):
     import torch
 
@@ -183,6 +212,8 @@ def main():
     ap.add_argument("--workload", default="tissue160")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain PyTorch comparison")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--jac-steps", type=int, default=2,
+                    help="registrations timed with use_jac on (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
                     help="registrations run with per-kernel HIP events after the timed ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -255,6 +286,11 @@ def main():
         import torch
         zero = torch.zeros_like(field)
         out["accuracy"] = {"fused": acc, "identity_dice": accuracy(p, zero)["dice"]}
+    if args.jac_steps > 0:
+        jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
+        out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}
+        if acc:
+            out["use_jac"]["accuracy"] = accuracy(p, jfield)
     if not args.no_plain:
         try:
             pms, plosses, pfield = run_plain(p, args.plain_steps, 0, params)

@@ -65,8 +65,11 @@ typedef struct {
   float adam_beta1;   /* Adam (Kingma & Ba) constants, bias corrected; the step     */
   float adam_beta2;   /*   count continues across levels                            */
   float adam_eps;
-  int   use_jac;      /* Algorithm 1's use_jac; must be 0 (Jacobian-free descent,
-                         as in all of the paper's experiments)                      */
+  int   use_jac;      /* Algorithm 1's use_jac: 0 = Jacobian-free descent (the
+                         Gateaux gradient, as in all of the paper's experiments);
+                         1 = Eulerian descent, direction J(phi)^T dU/dphi with
+                         J(phi) = I + grad d by central differences inside the grid
+                         and one-sided differences on its faces (Section 4.4.2)    */
 } fa_params;
 
 /* Default parameters: eta 0.5, sigma_grad 1.0, sigma_warp 0.5, window 5,

@@ -11,7 +11,8 @@ of the method and in its order:
 * Algorithm 1 ("FireANTs"): levels -> iterations -> {cost, Gateaux gradient,
   optimizer state update, retraction by composition} -> upsample.
 * Section 4.4.2 (Jacobian-free Eulerian descent): the descent direction is the
-  Gateaux derivative of the cost with respect to the warp.
+  Gateaux derivative of the cost with respect to the warp; with Algorithm 1's
+  use_jac on, it is the Eulerian direction J(phi)^T dU/dphi instead.
 * Section 4.4, "Adaptive optimization on diffeomorphisms": Adam runs on the
   sequence of directions, which all live in the tangent space at identity.
 * Appendix E (limitations of stationary velocity fields): the step scale is
@@ -36,6 +37,8 @@ the function that applies it):
   replicate boundary; sigma is in voxels of the current level.
 * Order inside one iteration: gradient -> Adam -> smooth (sigma_grad) ->
   normalise -> compose -> smooth (sigma_warp).
+* The Jacobian J(phi) = I + grad d of use_jac takes grad d by central
+  differences inside the grid and one-sided first differences on its faces.
 * Step normalisation follows the printed inequality with dx = 1 voxel:
   u = -eta * s / (2 max|s|), so no voxel moves more than eta/2.
 * Adam: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias corrected, the step count
@@ -58,7 +61,7 @@ __all__ = [
     "Params", "trilinear", "trilinear_dpos", "identity_grid", "warp_image",
     "box_sum", "window_count",
     "lncc_forward", "lncc_grad_warped", "gateaux_gradient", "adam_update",
-    "gaussian_weights", "gaussian_smooth", "normalise_step", "compose",
+    "eulerian_direction", "gaussian_weights", "gaussian_smooth", "normalise_step", "compose",
     "iterate", "level_shape", "downsample_image", "upsample_state", "register",
     "warp_labels_nearest", "dice", "jacobian_det", "singular_fraction",
 ]
@@ -76,6 +79,7 @@ class Params:
     beta1: float = 0.9
     beta2: float = 0.999
     adam_eps: float = 1e-8
+    use_jac: bool = False   # Algorithm 1's use_jac: Eulerian instead of Jacobian-free direction
 
 
 # ---------------------------------------------------------------------------
@@ -248,6 +252,20 @@ def gateaux_gradient(fixed, moving, d, window, eps):
 # Adam on the tangent space at identity (Section 4.4)
 # ---------------------------------------------------------------------------
 
+def eulerian_direction(g, d):
+    """Section 4.4.2, Eulerian descent: the direction J(phi)^T dU/dphi, with
+    J(phi)(x) = I + grad d(x) the Jacobian of phi = id + d.  Component a is
+    g_a + sum_c (d d_c / d x_a) g_c.  grad d: central differences inside the
+    grid, one-sided first differences on its faces (numpy.gradient)."""
+    g = np.asarray(g, np.float64)
+    d = np.asarray(d, np.float64)
+    out = g.copy()
+    for a in range(3):
+        for c in range(3):
+            out[a] += np.gradient(d[c], axis=a) * g[c]
+    return out
+
+
 def adam_update(g, m, v, t, beta1, beta2, eps):
     """One Adam step (Kingma & Ba) at step count ``t`` (already incremented).
 
@@ -323,6 +341,8 @@ def iterate(fixed, moving, d, m, v, t, P: Params):
     ``t`` is the Adam step count after increment.  Returns
     (d_new, m, v, L, extras) where extras holds the intermediates."""
     g, L = gateaux_gradient(fixed, moving, d, P.window, P.cc_eps)
+    if P.use_jac:
+        g = eulerian_direction(g, d)
     a, m, v = adam_update(g, m, v, t, P.beta1, P.beta2, P.adam_eps)
     s = gaussian_smooth(a, P.sigma_grad)
     u, M = normalise_step(s, P.eta)
@@ -380,7 +400,7 @@ def upsample_state(d, m, v, shape_f):
 
 
 def register(fixed, moving, scales, iters, P: Params, callback=None):
-    """Algorithm 1 with use_jac off (as in all of the paper's experiments).
+    """Algorithm 1 (use_jac as in P; off in all of the paper's experiments).
 
     Returns (d, losses, t): the displacement at the finest level, one loss per
     iteration (the cost before that iteration's update) and the final step

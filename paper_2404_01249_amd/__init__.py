@@ -23,13 +23,14 @@ class Pair:
     """
 
     def __init__(self, fixed, moving, *, eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5,
-                 cc_eps=1e-5, beta1=0.9, beta2=0.999, adam_eps=1e-8, stream=None):
+                 cc_eps=1e-5, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_jac=False, stream=None):
         import torch
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         p = fa.fa_params_default()
         p.eta, p.sigma_grad, p.sigma_warp, p.cc_window = eta, sigma_grad, sigma_warp, window
         p.cc_eps, p.adam_beta1, p.adam_beta2, p.adam_eps = cc_eps, beta1, beta2, adam_eps
+        p.use_jac = 1 if use_jac else 0
         self.params = p
         self.shape = tuple(int(s) for s in fixed.shape)
         self.handle = fa.fa_pair_create(fixed, moving, p, self.stream)

@@ -89,6 +89,11 @@ struct GaussArgs {
 // ---- launchers (fa_kernels.hip) -----------------------------------------
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s);
 hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s);
+// use_jac: the Eulerian direction J(phi)^T g (J = I + grad d, central
+// differences inside, one-sided on the faces), then Adam, in place over g in
+// ga (which receives the Adam direction); also clears M for the iteration.
+hipError_t launch_eulerian_adam(float* ga, const float* d, float* m, float* v, Ctl* ctl, int n0, int n1,
+                                int n2, float beta1, float beta2, float adam_eps, hipStream_t s);
 hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s);
 // out = in with a zero border of kPad voxels (padded_voxels(n0, n1, n2) floats).
 hipError_t launch_pad(const float* in, float* out, int n0, int n1, int n2, hipStream_t s);

@@ -1531,6 +1531,49 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube(const GaussArgs A
 // ---------------------------------------------------------------------------
 // Off-loop kernels: pyramid blur and resampling, warp, fills, layout copies.
 // ---------------------------------------------------------------------------
+// Algorithm 1 with use_jac: the descent direction is J(phi)^T dU/dphi
+// (Section 4.4.2, Eulerian descent), J(phi) = I + grad d; component a is
+// g_a + sum_c (d d_c / d x_a) g_c, with grad d by central differences inside
+// the grid and one-sided differences on its faces.  Adam follows, as in the
+// gradient kernel's own epilogue.  In place: each thread reads g only at the
+// voxel whose direction it writes.
+__global__ void __launch_bounds__(256)
+k_eulerian_adam(float* __restrict__ ga, const float* __restrict__ d, float* __restrict__ m,
+                float* __restrict__ v, Ctl* ctl, int n0, int n1, int n2, float beta1, float beta2,
+                float adam_eps) {
+  const int N = n0 * n1 * n2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mbits = 0u;   // M of this iteration
+  const float ibc1 = 1.0f / ctl->bc1, ibc2 = 1.0f / ctl->bc2;
+  const int plane = n1 * n2;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const int x2 = i % n2, t = i / n2;
+    const int x1 = t % n1, x0 = t / n1;
+    const int xs[3] = {x0, x1, x2}, ns[3] = {n0, n1, n2}, st[3] = {plane, n2, 1};
+    float g[3], out[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = ga[c * N + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const bool has_lo = xs[a] > 0, has_hi = xs[a] < ns[a] - 1;
+      const int lo = has_lo ? i - st[a] : i, hi = has_hi ? i + st[a] : i;
+      const float h = (has_lo && has_hi) ? 0.5f : 1.0f;
+      float r = g[a];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r += (d[c * N + hi] - d[c * N + lo]) * h * g[c];
+      out[a] = r;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int iq = q * N + i;
+      const float mm = beta1 * m[iq] + (1.0f - beta1) * out[q];
+      const float vv = beta2 * v[iq] + (1.0f - beta2) * out[q] * out[q];
+      m[iq] = mm;
+      v[iq] = vv;
+      ga[iq] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + adam_eps);
+    }
+  }
+}
+
 // Copy of a volume with a zero border of kPad voxels on every side.
 __global__ void k_pad(const float* __restrict__ in, float* __restrict__ out, int n0, int n1, int n2) {
   const int p0 = n0 + 2 * kPad, p1 = n1 + 2 * kPad, p2 = n2 + 2 * kPad;
@@ -1825,6 +1868,15 @@ hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tili
 
 
 static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_eulerian_adam(float* ga, const float* d, float* m, float* v, Ctl* ctl, int n0, int n1,
+                                int n2, float beta1, float beta2, float adam_eps, hipStream_t s) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_eulerian_adam, dim3(blocks), dim3(256), 0, s, ga, d, m, v, ctl, n0, n1, n2, beta1, beta2,
+                     adam_eps);
+  return hipGetLastError();
+}
 
 hipError_t launch_pad(const float* in, float* out, int n0, int n1, int n2, hipStream_t s) {
   const int64_t total = (int64_t)(n0 + 2 * kPad) * (n1 + 2 * kPad) * (n2 + 2 * kPad);

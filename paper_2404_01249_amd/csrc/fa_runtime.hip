@@ -153,7 +153,7 @@ fa_status check_params(const fa_params* p) {
     return fail(FA_EINVAL, "sigma_grad and sigma_warp must be finite");
   if (tap_radius(p->sigma_grad) > fa::kMaxRadius || tap_radius(p->sigma_warp) > fa::kMaxRadius)
     return fail(FA_EINVAL, "Gaussian radius ceil(3 sigma) must be <= 6 (sigma <= 2 voxels)");
-  if (p->use_jac != 0) return fail(FA_EINVAL, "use_jac = 1 (Jacobian-augmented descent) is not supported");
+  if (p->use_jac != 0 && p->use_jac != 1) return fail(FA_EINVAL, "use_jac must be 0 or 1");
   return FA_OK;
 }
 
@@ -235,8 +235,13 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   ga.beta2 = P->p.adam_beta2;
   ga.adam_eps = P->p.adam_eps;
   ga.inv_n = (float)(1.0 / (double)L.n);
-  ga.mode = 0;
+  // use_jac: the kernel writes the Gateaux gradient, and a second launch turns
+  // it into the Eulerian direction and applies Adam
+  ga.mode = P->p.use_jac ? 1 : 0;
   FA_HIP(fa::launch_grad(ga, w, L.tg, P->stream));
+  if (P->p.use_jac)
+    FA_HIP(fa::launch_eulerian_adam(P->a, P->d, P->m, P->v, P->ctl, L.shape.n0, L.shape.n1, L.shape.n2,
+                                    P->p.adam_beta1, P->p.adam_beta2, P->p.adam_eps, P->stream));
   if (P->profiling) FA_HIP(hipEventRecord(pe.e[1], P->stream));
 
   fa::GaussArgs gs{};

@@ -49,7 +49,7 @@ def _create_raw(lib, params, shape=(8, 8, 8), ptrs=(1, 2)):
 
 
 @pytest.mark.parametrize("field,value", [("cc_window", 4), ("cc_window", 11), ("cc_window", 0),
-                                         ("eta", 0.0), ("eta", -1.0), ("use_jac", 1),
+                                         ("eta", 0.0), ("eta", -1.0), ("use_jac", 2),
                                          ("sigma_grad", 2.5), ("adam_beta1", 1.0), ("cc_eps", -1.0)])
 def test_invalid_params_rejected_before_device_work(lib, field, value):
     p = fa.fa_params_default()

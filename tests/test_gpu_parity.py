@@ -131,6 +131,57 @@ def test_one_iteration_from_injected_state(shape, form):
     pr.close()
 
 
+@pytest.mark.parametrize("form", GRAD_FORMS)
+def test_one_iteration_with_use_jac(form):
+    """Algorithm 1 with use_jac: the Eulerian direction J(phi)^T g (Section
+    4.4.2) replaces the Gateaux gradient before Adam.  The displacement has
+    gradients of order 0.5, so the Jacobian term is far from negligible."""
+    shape = (21, 37, 45)
+    fixed, moving, _ = make_problem(shape, seed=37)
+    d = synth.smooth_field(shape, 38, sigma=2.0, max_norm=2.5)
+    rng = np.random.default_rng(39)
+    m = (1e-6 * rng.standard_normal((3,) + shape)).astype(np.float32)
+    v = (1e-12 * rng.random((3,) + shape)).astype(np.float32)
+    P = O.Params(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5, use_jac=True)
+    pr = new_pair(fixed, moving, eta=P.eta, sigma_grad=P.sigma_grad, sigma_warp=P.sigma_warp, window=5,
+                  use_jac=True)
+    fa.fa_pair_set_tuning(pr.handle, 0, 0, 0, 0, form)
+    pr.set_schedule([1.0], [1])
+    pr.set_state(dev(d), dev(m), dev(v), 4)
+    pr.step(1)
+    d1, m1, v1 = (host(x) for x in pr.state())
+    a = host(pr.direction())
+    ref_d, ref_m, ref_v, ref_L, ex = O.iterate(fixed, moving, d.astype(np.float64), m.astype(np.float64),
+                                               v.astype(np.float64), 5, P)
+    g_plain, _ = O.gateaux_gradient(fixed, moving, d, 5, 1e-5)
+    assert rel_l2(O.eulerian_direction(g_plain, d), g_plain) > 0.05     # the term matters here
+    assert abs(pr.loss_history()[-1] - ref_L) <= TOL_L * abs(ref_L)
+    assert rel_l2(m1, ref_m) <= TOL_G
+    assert rel_l2(v1, ref_v) <= TOL_G
+    assert rel_l2(a, ex["a"]) <= TOL_G
+    assert abs(pr.step_norm() - ex["M"]) <= TOL_G * ex["M"]
+    assert rel_l2(d1 - d, ref_d - d) <= TOL_G
+    pr.close()
+
+
+def test_short_run_with_use_jac_matches_oracle():
+    shape = (21, 37, 45)
+    fixed, moving, _ = make_problem(shape, seed=40, field_max=2.5)
+    P = O.Params(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5, use_jac=True)
+    pr = new_pair(fixed, moving, window=5, use_jac=True)
+    pr.set_schedule([2.0, 1.0], [8, 6])
+    pr.run()
+    loss = pr.loss_history().astype(np.float64)
+    d = host(pr.field())
+    d_ref, loss_ref, _ = O.register(fixed, moving, [2.0, 1.0], [8, 6], P)
+    rel = np.abs(loss - np.asarray(loss_ref)) / np.abs(np.asarray(loss_ref))
+    epe = float(np.sqrt(((d - d_ref) ** 2).sum(0)).mean())
+    print(f"use_jac run: loss rel max {rel.max():.2e}, mean endpoint diff {epe:.2e}", flush=True)
+    assert rel.max() <= 1e-4
+    assert epe <= 1e-3
+    pr.close()
+
+
 @pytest.mark.parametrize("eta,sigma_grad,sigma_warp", [(2.0, 0.3, 0.0), (3.0, 0.5, 1.0), (0.25, 0.0, 0.4),
                                                       (1.0, 2.0, 2.0)])
 def test_one_iteration_step_variants(eta, sigma_grad, sigma_warp):

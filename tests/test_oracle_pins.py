@@ -257,6 +257,60 @@ def test_gateaux_gradient_matches_torch_grid_sample_autograd():
 
 
 # ---------------------------------------------------------------------------
+# Eulerian direction (use_jac)
+# ---------------------------------------------------------------------------
+
+def test_eulerian_direction_is_identity_at_the_identity_map():
+    g = rand(3, 5, 6, 7, seed=40)
+    assert np.array_equal(O.eulerian_direction(g, np.zeros_like(g)), g)
+
+
+def _affine_field(n, A, b):
+    x = np.indices(n, dtype=np.float64)
+    return np.einsum("ca,a...->c...", A, x) + np.asarray(b)[:, None, None, None]
+
+
+def test_eulerian_direction_of_an_affine_map_is_the_transposed_jacobian():
+    """d = A x + b: J(phi) = I + A everywhere (central and one-sided differences
+    are exact for a linear field), and the direction is (I + A)^T g.  A is not
+    symmetric, so a transposed Jacobian fails."""
+    n = (5, 6, 7)
+    A = np.array([[0.1, -0.3, 0.2], [0.05, 0.2, -0.15], [0.4, 0.0, -0.1]])
+    d = _affine_field(n, A, [0.3, -0.2, 0.1])
+    g = rand(3, *n, seed=41)
+    ref = np.einsum("ca,c...->a...", np.eye(3) + A, g)
+    np.testing.assert_allclose(O.eulerian_direction(g, d), ref, rtol=1e-12, atol=1e-13)
+
+
+def test_eulerian_direction_predicts_the_cost_along_the_composed_path():
+    """Definition of the Eulerian differential (Section 4.4.2): the derivative
+    of U(phi o (id + eps v)) at eps = 0 is <J(phi)^T dU/dphi, v>.  With an
+    affine d, phi o (id + eps v) = phi + eps (I + A) v exactly (trilinear
+    interpolation reproduces an affine field), so central differences of the
+    cost along the composed path pin the direction; v vanishes on the faces so
+    that no sample leaves the grid.  The Gateaux direction alone misses the
+    term and fails the same check."""
+    n = (10, 11, 12)
+    fixed = ndi.gaussian_filter(rand(*n, seed=42), 1.5)
+    moving = ndi.gaussian_filter(rand(*n, seed=43), 1.5)
+    A = np.array([[0.15, -0.2, 0.1], [0.1, -0.12, 0.2], [-0.25, 0.05, 0.1]])
+    d = _affine_field(n, A, [0.37, -0.41, 0.23])
+    v = np.stack([ndi.gaussian_filter(rand(*n, seed=44 + c), 1.0) for c in range(3)])
+    v[:, [0, -1], :, :] = 0.0
+    v[:, :, [0, -1], :] = 0.0
+    v[:, :, :, [0, -1]] = 0.0
+    g, _ = O.gateaux_gradient(fixed, moving, d, 3, 1e-5)
+    eps = 1e-5
+    Up = O.lncc_forward(fixed, O.warp_image(moving, O.compose(d, eps * v)), 3, 1e-5)[1]
+    Um = O.lncc_forward(fixed, O.warp_image(moving, O.compose(d, -eps * v)), 3, 1e-5)[1]
+    fd = (Up - Um) / (2 * eps)
+    euler = float((O.eulerian_direction(g, d) * v).sum())
+    gateaux = float((g * v).sum())
+    assert euler == pytest.approx(fd, rel=1e-4)
+    assert abs(gateaux - fd) > 0.05 * abs(fd)
+
+
+# ---------------------------------------------------------------------------
 # Adam
 # ---------------------------------------------------------------------------
 
