@@ -15,6 +15,9 @@ Prints one JSON line.  Besides the headline value it reports
   the 8 TB/s HBM peak;
 * ``plain_torch``: the same algorithm written with stock PyTorch operators
   (grid_sample, conv3d, autograd, elementwise Adam) on the same GPU;
+* ``batch``: aggregate throughput of several registrations (step sizes of
+  the paper's grid search) advanced together on separate streams, against
+  the same registrations run one after another;
 * ``use_jac``: the same registration with Algorithm 1's use_jac on (the
   Eulerian direction J(phi)^T dU/dphi), its time relative to the default
   Jacobian-free form, and its accuracy;
@@ -142,6 +145,45 @@ def run_use_jac(p, steps, params):
     return start.elapsed_time(end) / steps, float(loss[-1]), field
 
 
+def run_batch_compare(p, k, params):
+    """k registrations of the workload, one per step size of the paper's
+    grid-search range (eta in 0.25, 0.5, 1, 2), first one after another on one
+    stream, then advanced together on k streams (fa_batch_step).  Returns the
+    seconds of each form (HIP-synchronised wall clock) after a warm-up."""
+    import torch
+
+    from paper_2404_01249_amd import Pair, run_batch
+    etas = [0.25, 0.5, 1.0, 2.0, 0.375, 0.75, 1.5, 3.0][:k]
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    base = {kk: vv for kk, vv in params.items() if kk != "eta"}
+    streams = [torch.cuda.Stream() for _ in etas]
+    pairs = [Pair(fixed, moving, stream=st, eta=e, **base) for st, e in zip(streams, etas)]
+    torch.cuda.synchronize()
+
+    def sequential():
+        for pr in pairs:
+            pr.set_schedule(p.scales, p.iters)
+            pr.run()
+            pr.stream.synchronize()
+
+    def together():
+        for pr in pairs:
+            pr.set_schedule(p.scales, p.iters)
+        run_batch(pairs)
+        torch.cuda.synchronize()
+
+    out = {}
+    for name, fn in (("sequential", sequential), ("batched", together)):
+        fn()
+        t0 = time.perf_counter()
+        fn()
+        out[name] = time.perf_counter() - t0
+    for pr in pairs:
+        pr.close()
+    return out
+
+
 def run_plain(p, steps, warmup, params):
     import torch
 
@@ -212,6 +254,8 @@ def main():
     ap.add_argument("--workload", default="tissue160")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain PyTorch comparison")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4,
+                    help="registrations run together on separate streams for the batch figure (0 skips)")
     ap.add_argument("--jac-steps", type=int, default=2,
                     help="registrations timed with use_jac on (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
@@ -286,6 +330,14 @@ def main():
         import torch
         zero = torch.zeros_like(field)
         out["accuracy"] = {"fused": acc, "identity_dice": accuracy(p, zero)["dice"]}
+    if args.batch > 0:
+        bt = run_batch_compare(p, min(args.batch, 8), params)
+        nb = min(args.batch, 8)
+        out["batch"] = {"registrations": nb, "streams": nb, "etas": [0.25, 0.5, 1.0, 2.0, 0.375, 0.75, 1.5, 3.0][:nb],
+                        "sequential_s": bt["sequential"], "batched_s": bt["batched"],
+                        "sequential_voxel_iters_per_s": nb * vox_iters / bt["sequential"],
+                        "batched_voxel_iters_per_s": nb * vox_iters / bt["batched"],
+                        "speedup": bt["sequential"] / bt["batched"]}
     if args.jac_steps > 0:
         jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
         out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}

@@ -11,7 +11,14 @@ from . import evaluate, fa
 from .fa import FAError
 from .lncc import LNCC
 
-__all__ = ["Pair", "FAError", "fa", "LNCC", "evaluate"]
+__all__ = ["Pair", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
+
+
+def run_batch(pairs, max_iters=1 << 30):
+    """Advance several :class:`Pair` objects together (fa_batch_step); pairs
+    created on different streams run concurrently.  Returns the number of
+    pairs whose schedule is complete."""
+    return fa.fa_batch_step([p.handle for p in pairs], max_iters)
 
 
 class Pair:

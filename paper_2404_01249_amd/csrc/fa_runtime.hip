@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "fa.h"
+#include "fa_batch.h"
 #include "fa_host.h"
 #include "fa_inspect.h"
 #include "fa_internal.h"
@@ -615,6 +616,37 @@ fa_status fa_pair_step(fa_pair P, int max_iters, int* iters_done, int* finished)
   }
   if (iters_done) *iters_done = done;
   if (finished) *finished = schedule_done(P) ? 1 : 0;
+  return FA_OK;
+}
+
+fa_status fa_batch_step(fa_pair* pairs, int n, int max_iters, int* n_finished) {
+  if (n_finished) *n_finished = 0;
+  if (n < 0 || (n > 0 && !pairs)) return fail(FA_EINVAL, "pairs is NULL or n < 0");
+  if (max_iters < 0) return fail(FA_EINVAL, "max_iters must be >= 0");
+  for (int i = 0; i < n; ++i) {
+    if (!pairs[i]) return fail(FA_EINVAL, "pairs[" + std::to_string(i) + "] is NULL");
+    if (!pairs[i]->scheduled) return fail(FA_ESTATE, "pairs[" + std::to_string(i) + "] has no schedule");
+    for (int j = 0; j < i; ++j)
+      if (pairs[j] == pairs[i]) return fail(FA_EINVAL, "a pair appears twice");
+  }
+  // one iteration per pair in turn: each stream always has work queued
+  std::vector<char> live(n, 1);
+  for (int k = 0; k < max_iters; ++k) {
+    int active = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!live[i]) continue;
+      int done = 0, fin = 0;
+      FA_TRY(fa_pair_step(pairs[i], 1, &done, &fin));
+      if (fin || done == 0) live[i] = 0;
+      active += live[i];
+    }
+    if (active == 0) break;
+  }
+  if (n_finished) {
+    int f = 0;
+    for (int i = 0; i < n; ++i) f += schedule_done(pairs[i]) ? 1 : 0;
+    *n_finished = f;
+  }
   return FA_OK;
 }
 

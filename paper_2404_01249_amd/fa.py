@@ -1,5 +1,5 @@
 """ctypes binding of the C ABI in include/fa.h, include/fa_inspect.h,
-include/fa_lncc.h and include/fa_eval.h.
+include/fa_batch.h, include/fa_lncc.h and include/fa_eval.h.
 
 Each function has the name of the C entry point it wraps and only marshals
 arguments: torch tensors become device pointers, the stream becomes its HIP
@@ -67,6 +67,7 @@ SIGNATURES = {
     "fa_pair_profile": (_I, [_P, _I]),
     "fa_pair_set_tuning": (_I, [_P, _I, _I, _I, _I, _I]),
     "fa_pair_get_profile": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_double), _IP]),
+    "fa_batch_step": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
     "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
     "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "fa_lncc_destroy": (None, [_P]),
@@ -289,3 +290,12 @@ def fa_jacobian_det(d, det_out=None, count: bool = True, stream=None) -> tuple[i
                                           ctypes.byref(nonpos) if count else None, ctypes.byref(interior),
                                           _stream_handle(stream)))
     return nonpos.value, interior.value
+
+
+# ---- include/fa_batch.h -------------------------------------------------------
+
+def fa_batch_step(pairs, max_iters: int) -> int:
+    arr = (_P * len(pairs))(*pairs)
+    fin = ctypes.c_int(0)
+    _check(load_library().fa_batch_step(arr, len(pairs), int(max_iters), ctypes.byref(fin)))
+    return fin.value

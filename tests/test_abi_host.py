@@ -71,3 +71,12 @@ def test_null_pointers_rejected(lib):
     assert lib.fa_pair_step(None, 1, None, None) == fa.FA_EINVAL
     assert lib.fa_pair_set_schedule(None, 1, None, None) == fa.FA_EINVAL
     lib.fa_pair_destroy(None)
+
+
+def test_batch_step_rejects_bad_arguments(lib):
+    fin = ctypes.c_int(7)
+    assert lib.fa_batch_step(None, 0, 1, ctypes.byref(fin)) == fa.FA_OK and fin.value == 0
+    assert lib.fa_batch_step(None, 2, 1, None) == fa.FA_EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.fa_batch_step(arr, 1, 1, None) == fa.FA_EINVAL
+    assert lib.fa_batch_step(arr, 1, -1, None) == fa.FA_EINVAL

@@ -318,6 +318,32 @@ def test_runs_are_bitwise_deterministic():
     assert np.array_equal(hist[0][1], hist[1][1])
 
 
+def test_batched_pairs_on_separate_streams_match_single_runs():
+    """Several registrations advanced together on their own streams give the
+    results of each run alone (bitwise: the same kernels on the same data)."""
+    from paper_2404_01249_amd import run_batch
+    fixed, moving, _ = make_problem((21, 37, 45), seed=72)
+    settings = [dict(eta=0.25), dict(eta=1.0, sigma_warp=0.0), dict(eta=2.0, use_jac=True)]
+    ref = []
+    for kw in settings:
+        pr = new_pair(fixed, moving, **kw)
+        pr.set_schedule([2.0, 1.0], [5, 4])
+        pr.run()
+        ref.append((pr.loss_history(), host(pr.field())))
+        pr.close()
+    streams = [torch.cuda.Stream() for _ in settings]
+    pairs = [Pair(dev(fixed), dev(moving), stream=st, **kw) for st, kw in zip(streams, settings)]
+    for pr in pairs:
+        pr.set_schedule([2.0, 1.0], [5, 4])
+    assert run_batch(pairs) == len(pairs)
+    for pr, (loss, field) in zip(pairs, ref):
+        assert np.array_equal(pr.loss_history(), loss)
+        got = pr.field()
+        pr.stream.synchronize()
+        assert np.array_equal(host(got), field)
+        pr.close()
+
+
 def test_step_before_schedule_is_a_state_error():
     fixed, moving, _ = make_problem((8, 9, 10), seed=81)
     pr = new_pair(fixed, moving)
