@@ -30,7 +30,8 @@ class SynthPair:
     name: str
     fixed: np.ndarray                 # float32 (n0, n1, n2)
     moving: np.ndarray                # float32 (n0, n1, n2)
-    true_field: np.ndarray            # float32 (3, n0, n1, n2): moving(x) = fixed(x + g(x))
+    true_field: np.ndarray | None     # float32 (3, n0, n1, n2): moving(x) = fixed(x + g(x)); None
+                                      # where it is not formed at full size
     fixed_labels: np.ndarray | None = None    # int8, classes 0..3 (label recipe only)
     moving_labels: np.ndarray | None = None
     scales: list = field(default_factory=list)
@@ -102,6 +103,86 @@ def tissue_pair(shape=(160, 192, 224), seed=2, label_sigma=4.0, bias_sigma=24.0,
                      fixed_labels=labels, moving_labels=mlab)
 
 
+def _coarse_field_at(rng, shape, spacing, max_norm, points):
+    """A smooth random displacement, evaluated only at `points` ((k, 3) voxel
+    coordinates): N(0,1) on a coarse grid of the given spacing, smoothed there,
+    interpolated with SciPy's order-1 spline, and scaled so that the largest
+    displacement over the coarse grid is max_norm."""
+    coarse = tuple(int(np.ceil((n - 1) / spacing)) + 1 for n in shape)
+    comps = [ndi.gaussian_filter(rng.standard_normal(coarse), 1.0, mode="reflect") for _ in range(3)]
+    scale = max_norm / np.sqrt(sum(c * c for c in comps)).max()
+    q = (np.asarray(points, np.float64) / spacing).T
+    return np.stack([scale * ndi.map_coordinates(c, q, order=1, mode="nearest") for c in comps], 1)
+
+
+def _stamp(vol, centre, cov_inv, amp, half):
+    """Adds amp * exp(-q^T C^-1 q / 2) on the box of half-width `half` around
+    `centre` (clipped to the volume)."""
+    lo = [max(0, int(np.floor(centre[k])) - half) for k in range(3)]
+    hi = [min(vol.shape[k], int(np.floor(centre[k])) + half + 1) for k in range(3)]
+    if any(h <= l for l, h in zip(lo, hi)):
+        return
+    q0, q1, q2 = (np.arange(lo[k], hi[k], dtype=np.float32) - np.float32(centre[k]) for k in range(3))
+    q0, q1, q2 = q0[:, None, None], q1[None, :, None], q2[None, None, :]
+    C = np.asarray(cov_inv, np.float32)
+    # the quadratic form, with the broadcast axes kept separate until the sum
+    e = (C[0, 0] * q0 * q0 + (2 * C[0, 1]) * q0 * q1) + ((2 * C[0, 2]) * q0 * q2 + C[1, 1] * q1 * q1) + \
+        ((2 * C[1, 2]) * q1 * q2 + C[2, 2] * q2 * q2)
+    vol[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] += np.float32(amp) * np.exp(np.float32(-0.5) * e)
+
+
+def microscopy_pair(shape=(512, 512, 512), seed=5, n_blobs=400, n_tubes=60, sigma_range=(2.0, 12.0),
+                    tube_radius=(1.5, 4.0), photons=100.0, field_max=20.0, name="microscopy"):
+    """Expansion-microscopy-like volume: anisotropic Gaussian blobs (per-axis
+    sigma in sigma_range, random orientation) and tubes along smoothed random
+    walks (Gaussian cross-section), with Poisson-like shot noise of variance
+    I / k (k photons per unit intensity).
+    The moving volume is the same scene with every structure displaced by a
+    smooth random field (max field_max voxels) evaluated where it lies: a
+    deformation of the scene, made without resampling the full volume, so the
+    pair stays cheap to generate at 512^3 (the field itself is not formed at
+    full size: true_field is None)."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(s) for s in shape)
+    field_rng = np.random.default_rng(seed + 2)
+    scene = []
+    for _ in range(n_blobs):
+        c = rng.uniform(0.0, 1.0, 3) * (np.array(shape) - 1)
+        sig = rng.uniform(*sigma_range, size=3)
+        Q, _r = np.linalg.qr(rng.standard_normal((3, 3)))
+        cov_inv = Q @ np.diag(1.0 / sig ** 2) @ Q.T
+        scene.append((c, cov_inv, rng.uniform(0.2, 1.0), int(np.ceil(3.0 * sig.max()))))
+    for _ in range(n_tubes):
+        steps = rng.normal(0.0, 8.0, size=(50, 3))
+        pts = rng.uniform(0.0, 1.0, 3) * (np.array(shape) - 1) + np.cumsum(steps, axis=0)
+        pts = ndi.gaussian_filter1d(pts, 5.0, axis=0, mode="nearest")
+        r = rng.uniform(*tube_radius)
+        amp = rng.uniform(0.3, 1.0)
+        seg = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+        t = np.concatenate([[0.0], np.cumsum(seg)])
+        sample = np.arange(0.0, t[-1], r)
+        cur = np.stack([np.interp(sample, t, pts[:, k]) for k in range(3)], 1)
+        cov_inv = np.eye(3) / (r * r)
+        for c in cur:
+            scene.append((c, cov_inv, amp * 0.4, int(np.ceil(3.0 * r))))
+    # the structure at y appears at y - g(y) in the moving volume, so that
+    # moving(x) = fixed(x + g(x)) to first order; g is formed only where needed
+    g = _coarse_field_at(field_rng, shape, 32, field_max, np.array([c for c, _, _, _ in scene]))
+    fixed = np.zeros(shape, np.float32)
+    moving = np.zeros(shape, np.float32)
+    for (c, cov_inv, amp, half), gc in zip(scene, g):
+        _stamp(fixed, c, cov_inv, amp, half)
+        _stamp(moving, c - gc, cov_inv, amp, half)
+    noise = np.random.default_rng(seed + 1)
+    for vol in (fixed, moving):
+        # shot noise of `photons` counts per unit intensity, in its Gaussian
+        # form (variance I / photons), clipped at zero
+        np.clip(vol, 0.0, None, out=vol)
+        vol += np.sqrt(vol / np.float32(photons)) * noise.standard_normal(shape, dtype=np.float32)
+        np.clip(vol, 0.0, None, out=vol)
+    return SynthPair(name, fixed, moving, None)
+
+
 def smooth_field(shape, seed, sigma=6.0, max_norm=2.0):
     """A smooth random displacement (float32, (3,)+shape) for gradient checks."""
     rng = np.random.default_rng(seed)
@@ -133,7 +214,16 @@ def blobs128():
     return p
 
 
-WORKLOADS = {"blobs64": blobs64, "tissue160": tissue160, "blobs128": blobs128}
+def microscopy128():
+    """128^3 microscopy-like pair, four levels (8x, 4x, 2x, 1x) at 40/20/10/5
+    iterations, LNCC 7^3: the 512^3 recipe's structure at a size the FP64
+    oracle runs in minutes."""
+    p = microscopy_pair((128, 128, 128), seed=5, n_blobs=60, n_tubes=8)
+    p.name, p.scales, p.iters, p.window = "microscopy128", [8.0, 4.0, 2.0, 1.0], [40, 20, 10, 5], 7
+    return p
+
+
+WORKLOADS = {"blobs64": blobs64, "tissue160": tissue160, "blobs128": blobs128, "microscopy128": microscopy128}
 
 
 def load(name: str, cache_dir: str | None = None) -> SynthPair:
@@ -144,7 +234,7 @@ def load(name: str, cache_dir: str | None = None) -> SynthPair:
     if os.path.exists(path):
         try:
             z = np.load(path, allow_pickle=False)
-            p = SynthPair(name, z["fixed"], z["moving"], z["true_field"],
+            p = SynthPair(name, z["fixed"], z["moving"], z["true_field"] if "true_field" in z else None,
                           z["fixed_labels"] if "fixed_labels" in z else None,
                           z["moving_labels"] if "moving_labels" in z else None)
             meta = _META[name]
@@ -155,7 +245,9 @@ def load(name: str, cache_dir: str | None = None) -> SynthPair:
     p = gen()
     try:
         os.makedirs(cache_dir, exist_ok=True)
-        arrays = dict(fixed=p.fixed, moving=p.moving, true_field=p.true_field)
+        arrays = dict(fixed=p.fixed, moving=p.moving)
+        if p.true_field is not None:
+            arrays["true_field"] = p.true_field
         if p.fixed_labels is not None:
             arrays.update(fixed_labels=p.fixed_labels, moving_labels=p.moving_labels)
         tmp = path + f".{os.getpid()}.tmp.npz"
@@ -170,4 +262,5 @@ _META = {
     "blobs64": ([2.0, 1.0], [100, 50], 5),
     "tissue160": ([4.0, 2.0, 1.0], [200, 100, 50], 5),
     "blobs128": ([1.0], [1], 5),
+    "microscopy128": ([8.0, 4.0, 2.0, 1.0], [40, 20, 10, 5], 7),
 }

@@ -5,6 +5,7 @@ value here comes from the HIP library.
 
     python tests/golden/make_golden.py blobs64      # ~1 min
     python tests/golden/make_golden.py tissue160    # ~25 min
+    python tests/golden/make_golden.py microscopy128  # ~3 min
 
 Each output ``<name>_oracle.npz`` holds the per-iteration loss history, the
 final displacement sampled on a strided grid (``field_stride``), the final
@@ -24,7 +25,7 @@ sys.path.insert(0, ROOT)
 import oracle as O  # noqa: E402
 from paper_2404_01249_amd import synth  # noqa: E402
 
-STRIDES = {"blobs64": 2, "tissue160": 4}
+STRIDES = {"blobs64": 2, "tissue160": 4, "microscopy128": 2}
 
 
 def main(name):

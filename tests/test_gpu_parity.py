@@ -305,6 +305,24 @@ def test_full_run_blobs64_matches_oracle(form):
     pr.close()
 
 
+def test_full_run_microscopy128_matches_oracle():
+    """Four-level run (8x, 4x, 2x, 1x at 40/20/10/5) with an LNCC window of
+    7^3 on the microscopy-like recipe, against the stored oracle run."""
+    p, gold, pr = _full_run("microscopy128")
+    loss = pr.loss_history().astype(np.float64)
+    ref = gold["losses"]
+    s = int(gold["field_stride"])
+    d = host(pr.field())[:, ::s, ::s, ::s]
+    epe = float(np.sqrt(((d - gold["field"]) ** 2).sum(0)).mean())
+    rel = np.abs(loss - ref) / np.abs(ref)
+    print(f"microscopy128 run: mean endpoint diff {epe:.4f} vox; loss rel first {rel[0]:.2e}, "
+          f"max {rel.max():.2e}", flush=True)
+    assert rel[0] <= TOL_L
+    assert epe <= 0.05
+    assert rel.max() <= 1e-2
+    pr.close()
+
+
 def test_runs_are_bitwise_deterministic():
     fixed, moving, _ = make_problem((21, 37, 45), seed=71)
     hist = []
