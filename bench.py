@@ -16,8 +16,9 @@ Prints one JSON line.  Besides the headline value it reports
 * ``plain_torch``: the same algorithm written with stock PyTorch operators
   (grid_sample, conv3d, autograd, elementwise Adam) on the same GPU;
 * ``batch``: aggregate throughput of several registrations (step sizes of
-  the paper's grid search) advanced together on separate streams, against
-  the same registrations run one after another;
+  the paper's grid search) advanced together, on separate streams and by
+  batched launches (one launch per kernel for all of them), against the same
+  registrations run one after another;
 * ``use_jac``: the same registration with Algorithm 1's use_jac on (the
   Eulerian direction J(phi)^T dU/dphi), its time relative to the default
   Jacobian-free form, and its accuracy;
@@ -147,9 +148,10 @@ def run_use_jac(p, steps, params):
 
 def run_batch_compare(p, k, params):
     """k registrations of the workload, one per step size of the paper's
-    grid-search range (eta in 0.25, 0.5, 1, 2), first one after another on one
-    stream, then advanced together on k streams (fa_batch_step).  Returns the
-    seconds of each form (HIP-synchronised wall clock) after a warm-up."""
+    grid-search range (eta in 0.25, 0.5, 1, 2): one after another on one
+    stream, advanced together on k streams (fa_batch_step), and advanced
+    together by batched launches (fa_batch_step_fused).  Returns the seconds
+    of each form (HIP-synchronised wall clock) after a warm-up."""
     import torch
 
     from paper_2404_01249_amd import Pair, run_batch
@@ -170,11 +172,17 @@ def run_batch_compare(p, k, params):
     def together():
         for pr in pairs:
             pr.set_schedule(p.scales, p.iters)
-        run_batch(pairs)
+        run_batch(pairs, fused=False)
+        torch.cuda.synchronize()
+
+    def fused():
+        for pr in pairs:
+            pr.set_schedule(p.scales, p.iters)
+        run_batch(pairs, fused=True)
         torch.cuda.synchronize()
 
     out = {}
-    for name, fn in (("sequential", sequential), ("batched", together)):
+    for name, fn in (("sequential", sequential), ("batched", together), ("fused", fused)):
         fn()
         t0 = time.perf_counter()
         fn()
@@ -255,7 +263,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain PyTorch comparison")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4,
-                    help="registrations run together on separate streams for the batch figure (0 skips)")
+                    help="registrations run together (streams, then batched launches) for the batch figure (0 skips)")
     ap.add_argument("--jac-steps", type=int, default=2,
                     help="registrations timed with use_jac on (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
@@ -333,11 +341,14 @@ def main():
     if args.batch > 0:
         bt = run_batch_compare(p, min(args.batch, 8), params)
         nb = min(args.batch, 8)
-        out["batch"] = {"registrations": nb, "streams": nb, "etas": [0.25, 0.5, 1.0, 2.0, 0.375, 0.75, 1.5, 3.0][:nb],
-                        "sequential_s": bt["sequential"], "batched_s": bt["batched"],
+        out["batch"] = {"registrations": nb, "etas": [0.25, 0.5, 1.0, 2.0, 0.375, 0.75, 1.5, 3.0][:nb],
+                        "sequential_s": bt["sequential"], "streams_s": bt["batched"],
+                        "fused_s": bt["fused"],
                         "sequential_voxel_iters_per_s": nb * vox_iters / bt["sequential"],
-                        "batched_voxel_iters_per_s": nb * vox_iters / bt["batched"],
-                        "speedup": bt["sequential"] / bt["batched"]}
+                        "streams_voxel_iters_per_s": nb * vox_iters / bt["batched"],
+                        "fused_voxel_iters_per_s": nb * vox_iters / bt["fused"],
+                        "streams_speedup": bt["sequential"] / bt["batched"],
+                        "fused_speedup": bt["sequential"] / bt["fused"]}
     if args.jac_steps > 0:
         jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
         out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}

@@ -4,11 +4,12 @@
  * settings, as in the paper's grid searches (Results, "FireANTs enables rapid
  * prototyping and hyperparameter tuning").
  *
- * Each pair keeps its own state, schedule, step norm M and loss history, and
- * runs its kernels on the HIP stream it was created with.  Pairs created on
- * different streams therefore run concurrently on the GPU: the coarse pyramid
- * levels of one registration leave most of the chip idle, and the other
- * registrations fill it.
+ * Each pair keeps its own state, schedule, step norm M and loss history.
+ * fa_batch_step runs each pair's kernels on the HIP stream it was created
+ * with, so pairs created on different streams run concurrently on the GPU;
+ * fa_batch_step_fused runs one launch per kernel for the whole batch.  Either
+ * way the coarse pyramid levels of one registration, which leave most of the
+ * chip idle, are filled by the other registrations.
  */
 #ifndef FA_BATCH_H_
 #define FA_BATCH_H_
@@ -26,6 +27,29 @@ extern "C" {
  * synchronise.  Results are those of fa_pair_step on each pair alone.  A pair
  * must not appear twice.  On an error no further pair is advanced. */
 fa_status fa_batch_step(fa_pair* pairs, int n, int max_iters, int* n_finished);
+
+/* The same advance with batched launches: each kernel of an iteration of
+ * Algorithm 1 (fused gradient + Adam, sigma_grad smoothing with the max norm,
+ * composition, sigma_warp smoothing with the loss record) runs as ONE launch
+ * for all the pairs that share its template parameters -- cost window, Gaussian
+ * radius, composition form and the tile form of the pair's current level --
+ * and as one launch per such group otherwise.  Pairs may differ in size,
+ * level, schedule and every parameter; each keeps its own M, Adam step count
+ * and loss history (per-pair control blocks), and its results are bitwise
+ * those of fa_pair_step on the pair alone.  The use_jac direction stays one
+ * launch per pair.
+ *
+ * Streams: all the work of the call is enqueued on pairs[0]'s stream, which
+ * first waits for the work already queued on the other pairs' streams; at the
+ * end those streams wait for it.  The call synchronises with that stream when
+ * the batch's composition changes (a level transition or a finished pair:
+ * the launch tables are uploaded then) and before it returns.  All pairs must
+ * be on one device.  The per-kernel timing of fa_pair_profile does not cover
+ * iterations run here.  Errors: FA_EINVAL (NULL or repeated pair, n < 0,
+ * max_iters < 0, pairs on different devices), FA_ESTATE (a pair without a
+ * schedule), FA_ENOMEM (launch tables), FA_EHIP; after an error the pairs
+ * already advanced keep their progress. */
+fa_status fa_batch_step_fused(fa_pair* pairs, int n, int max_iters, int* n_finished);
 
 #ifdef __cplusplus
 }

@@ -75,6 +75,18 @@ fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_m
  * the launch shape beyond floating-point summation order. */
 fa_status fa_pair_set_tuning(fa_pair pair, int kind, int ty, int tx, int zc, int variant);
 
+/* Host-only view of the automatic march launch shapes (no GPU involved).
+ * kind as in fa_pair_set_tuning; shapes: n volumes (host array).
+ * batched = 0: each volume's own launch (the chunk fa_pair_step uses);
+ * batched = 1: the chunks of one batched launch over all n volumes, as
+ * fa_batch_step_fused chooses them, with `halo` planes recomputed per chunk
+ * (4 * (window / 2) for kind 0, 2 * radius for kinds 1 and 2, 2 for kind 3).
+ * zc_out and blocks_out (host, n ints each, may be NULL) receive the planes
+ * per workgroup and the workgroups of each volume.  FA_EINVAL for a bad kind,
+ * n < 1, halo < 0 or NULL shapes; FA_ESHAPE for an invalid shape. */
+fa_status fa_plan_tiling(int kind, int n, const fa_shape* shapes, int halo, int batched, int* zc_out,
+                         int* blocks_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,11 +14,14 @@ from .lncc import LNCC
 __all__ = ["Pair", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
 
 
-def run_batch(pairs, max_iters=1 << 30):
-    """Advance several :class:`Pair` objects together (fa_batch_step); pairs
-    created on different streams run concurrently.  Returns the number of
-    pairs whose schedule is complete."""
-    return fa.fa_batch_step([p.handle for p in pairs], max_iters)
+def run_batch(pairs, max_iters=1 << 30, fused=True):
+    """Advance several :class:`Pair` objects together.  fused=True
+    (fa_batch_step_fused): one launch per kernel for all pairs that share its
+    template parameters.  fused=False (fa_batch_step): each pair on its own
+    stream, interleaved.  Returns the number of pairs whose schedule is
+    complete."""
+    fn = fa.fa_batch_step_fused if fused else fa.fa_batch_step
+    return fn([p.handle for p in pairs], max_iters)
 
 
 class Pair:

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "fa.h"
 #include "fa_internal.h"
@@ -35,6 +36,13 @@ enum KernelKind { KIND_GRAD = 0, KIND_SMOOTH_MAX = 1, KIND_WARP_SMOOTH = 2, KIND
 // exists for the kernel's radius and epilogue (smoothing and composition
 // kinds only).
 Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu = Tuning(), bool cube_ok = false);
+
+// Chunk lengths of the march tilings ts (one per entry of a batched launch of
+// kernel `kind`, volumes of n0s[i] planes along n0, `halo` planes recomputed
+// per chunk) for the resident slots they share; entries with pinned[i] keep
+// their chunk.  Brick tilings are left as they are.
+void batch_chunks(KernelKind kind, int halo, const std::vector<Tiling*>& ts, const std::vector<int>& n0s,
+                  const std::vector<char>& pinned);
 
 }  // namespace fa
 

@@ -86,9 +86,32 @@ struct GaussArgs {
   int zc, tiles_y, tiles_x;
 };
 
+// ---- batched launches ----------------------------------------------------
+// One registration's share of a batched launch: its arguments and its range
+// [first, first + nblocks) of the launch's workgroups (tile order, after the
+// XCD renumbering).  owner[g] (one int per workgroup) names the entry of
+// workgroup g.  Every entry of one launch shares the kernel's template
+// parameters (window or radius, tile shape, brick or march, epilogue).
+template <class Args>
+struct BatchEntry {
+  Args a;
+  int first;
+  int nblocks;
+};
+
 // ---- launchers (fa_kernels.hip) -----------------------------------------
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s);
 hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s);
+// Batched forms: `total` workgroups over the entries E (device memory) with
+// owner (device memory, `total` ints); t gives the template parameters only
+// (tile shape, brick or march) and must be the tiling of every entry.
+hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
+                             const Tiling& t, hipStream_t s);
+hipError_t launch_gauss_batch(const BatchEntry<GaussArgs>* E, const int* owner, int total, int radius,
+                              int epilogue, const Tiling& t, hipStream_t s);
+// Whether a batched form exists for these parameters.
+bool grad_batch_supported(int window, const Tiling& t);
+bool gauss_batch_supported(int radius, int epilogue, const Tiling& t);
 // use_jac: the Eulerian direction J(phi)^T g (J = I + grad d, central
 // differences inside, one-sided on the faces), then Adam, in place over g in
 // ga (which receives the Adam direction); also clears M for the iteration.

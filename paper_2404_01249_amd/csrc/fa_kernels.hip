@@ -385,7 +385,7 @@ __device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex)
 }
 
 template <int W, int TY, int TX, bool PIPE>
-__device__ __forceinline__ void grad_body(const GradArgs& A) {
+__device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   constexpr int R = W / 2;
   constexpr int NT = TY * TX;
   constexpr int E1Y = TY + 4 * R, E1X = TX + 4 * R, E1 = E1Y * E1X;
@@ -412,7 +412,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
-  int b = xcd_tile(blockIdx.x, gridDim.x);
+  int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -466,7 +466,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
   }
 
   const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
-  if (A.mode == 0 && blockIdx.x == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
+  if (A.mode == 0 && tile == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
   const float gsc = (A.mode == 1 && A.gscale) ? *A.gscale : 1.0f;
   float lacc = 0.0f;   // this thread's cc sum over at most 2 zc columns
@@ -753,19 +753,19 @@ __device__ __forceinline__ void grad_body(const GradArgs& A) {
     for (int k = 0; k < CPT1; ++k) finish_gather(k);
   }
   const double tot = block_sum<NT>((double)lacc, red);
-  if (tid == 0) A.partials[blockIdx.x] = tot;
+  if (tid == 0) A.partials[tile] = tot;
 }
 
 template <int W, int TY, int TX, bool PIPE>
 __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
-  grad_body<W, TY, TX, PIPE>(A);
+  grad_body<W, TY, TX, PIPE>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // The same kernel compiled for two workgroups per CU (at most 128 VGPRs);
 // used where that fits without spilling.
 template <int W, int TY, int TX, bool PIPE>
 __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4))) k_grad_o4(const GradArgs A) {
-  grad_body<W, TY, TX, PIPE>(A);
+  grad_body<W, TY, TX, PIPE>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -782,12 +782,12 @@ __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)
 // completion count needs no memory fences: only the atomic itself, which
 // hands the epilogue to exactly one workgroup.
 template <int NT>
-__device__ __forceinline__ void finish_iteration(const GaussArgs& A, double* red, int* is_last) {
+__device__ __forceinline__ void finish_iteration(const GaussArgs& A, double* red, int* is_last, int nblocks) {
   const int tid = threadIdx.x;
   __syncthreads();
   if (tid == 0) {
     const unsigned prev = atomicAdd(&A.ctl->ticket, 1u);
-    *is_last = (prev == gridDim.x - 1) ? 1 : 0;
+    *is_last = (prev == (unsigned)nblocks - 1u) ? 1 : 0;
   }
   __syncthreads();
   if (*is_last) {
@@ -808,7 +808,7 @@ __device__ __forceinline__ void finish_iteration(const GaussArgs& A, double* red
 }
 
 template <int R, int TY, int TX, int EPI>
-__global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
+__device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, const int nblocks) {
   constexpr int L = 2 * R + 1;
   constexpr int NT = TY * TX;
   constexpr int EY = TY + 2 * R, EX = TX + 2 * R, E = EY * EX;
@@ -824,7 +824,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
   __shared__ int is_last;
 
   const int tid = threadIdx.x;
-  int b = xcd_tile(blockIdx.x, gridDim.x);
+  int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -1065,7 +1065,7 @@ __global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
   }
-  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last);
+  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last, nblocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1095,7 +1095,7 @@ struct GradCubeShape {
 };
 
 template <int W, int TZ, int TY, int TX>
-__global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
+__device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile) {
   using S = GradCubeShape<W, TZ, TY, TX>;
   constexpr int R = S::R;
   constexpr int NT = TZ * TY * TX;
@@ -1108,7 +1108,7 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
-  int b = xcd_tile(blockIdx.x, gridDim.x);
+  int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -1117,7 +1117,7 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
   const int N = n0 * n1 * n2;
   const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
-  if (A.mode == 0 && blockIdx.x == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
+  if (A.mode == 0 && tile == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
 
   // the thread's own output voxel: I, J and grad_p I_m, Adam moments
   const int tz = tid / (TY * TX), tr = tid - tz * (TY * TX);
@@ -1324,7 +1324,7 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
     }
   }
   const double tot = block_sum<NT>((double)lacc, red);
-  if (tid == 0) A.partials[blockIdx.x] = tot;
+  if (tid == 0) A.partials[tile] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -1336,7 +1336,7 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
 // steps long instead of one step per plane of a chunk plus its halo.
 // ---------------------------------------------------------------------------
 template <int R, int TZ, int TY, int TX, int EPI>
-__global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube(const GaussArgs A) {
+__device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int tile, const int nblocks) {
   constexpr int L = 2 * R + 1;
   constexpr int NT = TZ * TY * TX;
   constexpr int RZ = TZ + 2 * R, RY = TY + 2 * R, RX = TX + 2 * R;
@@ -1351,7 +1351,7 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube(const GaussArgs A) 
   __shared__ int is_last;
 
   const int tid = threadIdx.x;
-  int b = xcd_tile(blockIdx.x, gridDim.x);
+  int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -1444,19 +1444,19 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube(const GaussArgs A) 
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
   }
-  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last);
+  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last, nblocks);
 }
 
 // d' = u + d(x + u), u = -eta s / (2M), |u| <= 1 voxel, on a brick: d is
 // staged in LDS on the brick plus one voxel (zero off the grid).  Runs in
 // place over s: each thread reads s only at the voxel it writes.
 template <int TZ, int TY, int TX>
-__global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube(const GaussArgs A) {
+__device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int tile) {
   constexpr int NT = TZ * TY * TX;
   constexpr int DZ = TZ + 2, DY = TY + 2, DX = TX + 2, DE = DZ * DY * DX;
   extern __shared__ float lds[];   // [3][DE]
   const int tid = threadIdx.x;
-  int b = xcd_tile(blockIdx.x, gridDim.x);
+  int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
   const int by = b % A.tiles_y;
@@ -1526,6 +1526,157 @@ __global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube(const GaussArgs A
     A.out[N + idx] = u1 + res[1];
     A.out[2 * N + idx] = u2 + res[2];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels of the iteration, in two forms.  The plain form runs one
+// registration, with its arguments in the kernel arguments.  The batch form
+// runs several registrations in one launch: entry e of a table in device
+// memory holds the arguments of one registration and its range of
+// workgroups in the launch, and owner[g] names the entry of workgroup g
+// (after the XCD renumbering, so each XCD takes a contiguous range of the
+// batch's tiles).  A workgroup loads its entry's arguments once, with scalar
+// loads, and then runs the same body as the plain form.
+// ---------------------------------------------------------------------------
+// A pointer loaded from memory is generic to the compiler, and accesses
+// through it become flat instructions (which also count against the LDS
+// wait counter, so every LDS wait would wait for them too).  Each pointer is
+// rebuilt from its integer value as a global-address-space pointer, which
+// tells the compiler what it knows for kernel arguments: the body then uses
+// global instructions.  (A plain cast to the global space and back is folded
+// away before the address spaces are inferred.)
+template <class T>
+__device__ __forceinline__ T* as_global(T* p) {
+  typedef __attribute__((address_space(1))) T GT;
+  return (T*)(GT*)(uintptr_t)p;
+}
+
+__device__ __forceinline__ void load_args(const GradArgs* __restrict__ s, GradArgs& A) {
+  A.fixed = as_global(s->fixed);
+  A.moving_pad = as_global(s->moving_pad);
+  A.d = as_global(s->d);
+  A.m = as_global(s->m);
+  A.v = as_global(s->v);
+  A.out = as_global(s->out);
+  A.gscale = as_global(s->gscale);
+  A.partials = as_global(s->partials);
+  A.ctl = as_global(s->ctl);
+  A.n0 = s->n0;
+  A.n1 = s->n1;
+  A.n2 = s->n2;
+  A.zc = s->zc;
+  A.tiles_y = s->tiles_y;
+  A.tiles_x = s->tiles_x;
+  A.eps_cc = s->eps_cc;
+  A.beta1 = s->beta1;
+  A.beta2 = s->beta2;
+  A.adam_eps = s->adam_eps;
+  A.inv_n = s->inv_n;
+  A.mode = s->mode;
+}
+
+__device__ __forceinline__ void load_args(const GaussArgs* __restrict__ s, GaussArgs& A) {
+  A.in = as_global(s->in);
+  A.out = as_global(s->out);
+  A.d = as_global(s->d);
+  A.wts = as_global(s->wts);
+  A.ctl = as_global(s->ctl);
+  A.partials = as_global(s->partials);
+  A.loss_hist = as_global(s->loss_hist);
+  A.loss_cap = s->loss_cap;
+  A.n_partials = s->n_partials;
+  A.inv_n = s->inv_n;
+  A.eta = s->eta;
+  A.n0 = s->n0;
+  A.n1 = s->n1;
+  A.n2 = s->n2;
+  A.zc = s->zc;
+  A.tiles_y = s->tiles_y;
+  A.tiles_x = s->tiles_x;
+}
+
+template <class Args>
+__device__ __forceinline__ int batch_entry(const BatchEntry<Args>* __restrict__ E, const int* __restrict__ owner,
+                                           Args& A, int& nblocks) {
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const int e = owner[g];
+  load_args(&E[e].a, A);
+  nblocks = E[e].nblocks;
+  return g - E[e].first;
+}
+
+template <int W, int TY, int TX>
+__global__ void __launch_bounds__(TY * TX) k_grad_batch(const BatchEntry<GradArgs>* __restrict__ E,
+                                                        const int* __restrict__ owner) {
+  GradArgs A;
+  int nb;
+  const int tile = batch_entry(E, owner, A, nb);
+  grad_body<W, TY, TX, true>(A, tile);
+}
+
+template <int W, int TY, int TX>
+__global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)))
+k_grad_o4_batch(const BatchEntry<GradArgs>* __restrict__ E, const int* __restrict__ owner) {
+  GradArgs A;
+  int nb;
+  const int tile = batch_entry(E, owner, A, nb);
+  grad_body<W, TY, TX, true>(A, tile);
+}
+
+template <int R, int TY, int TX, int EPI>
+__global__ void __launch_bounds__(TY * TX) k_gauss(const GaussArgs A) {
+  gauss_body<R, TY, TX, EPI>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+template <int R, int TY, int TX, int EPI>
+__global__ void __launch_bounds__(TY * TX) k_gauss_batch(const BatchEntry<GaussArgs>* __restrict__ E,
+                                                         const int* __restrict__ owner) {
+  GaussArgs A;
+  int nb;
+  const int tile = batch_entry(E, owner, A, nb);
+  gauss_body<R, TY, TX, EPI>(A, tile, nb);
+}
+
+template <int W, int TZ, int TY, int TX>
+__global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
+  grad_cube_body<W, TZ, TY, TX>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <int W, int TZ, int TY, int TX>
+__global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube_batch(const BatchEntry<GradArgs>* __restrict__ E,
+                                                                  const int* __restrict__ owner) {
+  GradArgs A;
+  int nb;
+  const int tile = batch_entry(E, owner, A, nb);
+  grad_cube_body<W, TZ, TY, TX>(A, tile);
+}
+
+template <int R, int TZ, int TY, int TX, int EPI>
+__global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube(const GaussArgs A) {
+  gauss_cube_body<R, TZ, TY, TX, EPI>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+template <int R, int TZ, int TY, int TX, int EPI>
+__global__ void __launch_bounds__(TZ * TY * TX) k_gauss_cube_batch(const BatchEntry<GaussArgs>* __restrict__ E,
+                                                                   const int* __restrict__ owner) {
+  GaussArgs A;
+  int nb;
+  const int tile = batch_entry(E, owner, A, nb);
+  gauss_cube_body<R, TZ, TY, TX, EPI>(A, tile, nb);
+}
+
+template <int TZ, int TY, int TX>
+__global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube(const GaussArgs A) {
+  compose_cube_body<TZ, TY, TX>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <int TZ, int TY, int TX>
+__global__ void __launch_bounds__(TZ * TY * TX) k_compose_cube_batch(const BatchEntry<GaussArgs>* __restrict__ E,
+                                                                     const int* __restrict__ owner) {
+  GaussArgs A;
+  int nb;
+  const int tile = batch_entry(E, owner, A, nb);
+  compose_cube_body<TZ, TY, TX>(A, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -1824,6 +1975,115 @@ hipError_t grad_launch_cube(const GradArgs& a, int window, const Tiling& t, hipS
   }
 }
 
+// ---- batched launches ------------------------------------------------------
+template <int W, int TY, int TX>
+hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int total, hipStream_t s) {
+  constexpr size_t sh = grad_lds<W, TY, TX>();
+  constexpr bool occ2 = (W <= 5) && TY == 16 && TX == 32;
+  const dim3 g(total), blk(TY * TX);
+  if constexpr (occ2) k_grad_o4_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
+  else k_grad_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
+  return hipGetLastError();
+}
+
+template <int TY, int TX>
+hipError_t grad_batch_tile(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
+                           hipStream_t s) {
+  switch (window) {
+    case 1: return grad_batch_t<1, TY, TX>(E, owner, total, s);
+    case 3: return grad_batch_t<3, TY, TX>(E, owner, total, s);
+    case 5: return grad_batch_t<5, TY, TX>(E, owner, total, s);
+    case 7: return grad_batch_t<7, TY, TX>(E, owner, total, s);
+    case 9: return grad_batch_t<9, TY, TX>(E, owner, total, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int W>
+hipError_t grad_cube_batch_w(const BatchEntry<GradArgs>* E, const int* owner, int total, hipStream_t s) {
+  constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
+  constexpr size_t sh = GradCubeShape<W, TZ, TY, TX>::lds_bytes;
+  static bool attr_set = false;   // raise the dynamic LDS limit once per process
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube_batch<W, TZ, TY, TX>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  k_grad_cube_batch<W, TZ, TY, TX><<<dim3(total), dim3(TZ * TY * TX), sh, s>>>(E, owner);
+  return hipGetLastError();
+}
+
+template <int R, int TY, int TX>
+hipError_t gauss_batch_r(const BatchEntry<GaussArgs>* E, const int* owner, int total, int epi, hipStream_t s) {
+  const dim3 g(total), blk(TY * TX);
+  const size_t sh = gauss_lds<R, TY, TX>(epi == EPI_COMPOSE_LDS);
+  switch (epi) {
+    case EPI_SMOOTH_MAX: k_gauss_batch<R, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(E, owner); break;
+    case EPI_STORE_FINAL: k_gauss_batch<R, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(E, owner); break;
+    case EPI_COMPOSE_LDS:
+    case EPI_COMPOSE:
+      // the composition runs with the single tap (radius 0) only
+      if constexpr (R == 0) {
+        if (epi == EPI_COMPOSE_LDS) k_gauss_batch<0, TY, TX, EPI_COMPOSE_LDS><<<g, blk, sh, s>>>(E, owner);
+        else k_gauss_batch<0, TY, TX, EPI_COMPOSE><<<g, blk, sh, s>>>(E, owner);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int TY, int TX>
+hipError_t gauss_batch_tile(const BatchEntry<GaussArgs>* E, const int* owner, int total, int radius, int epi,
+                            hipStream_t s) {
+  switch (radius) {
+    case 0: return gauss_batch_r<0, TY, TX>(E, owner, total, epi, s);
+    case 1: return gauss_batch_r<1, TY, TX>(E, owner, total, epi, s);
+    case 2: return gauss_batch_r<2, TY, TX>(E, owner, total, epi, s);
+    case 3: return gauss_batch_r<3, TY, TX>(E, owner, total, epi, s);
+    case 4: return gauss_batch_r<4, TY, TX>(E, owner, total, epi, s);
+    case 5: return gauss_batch_r<5, TY, TX>(E, owner, total, epi, s);
+    case 6: return gauss_batch_r<6, TY, TX>(E, owner, total, epi, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int R>
+hipError_t gauss_cube_batch_r(const BatchEntry<GaussArgs>* E, const int* owner, int total, int epi,
+                              hipStream_t s) {
+  constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
+  constexpr size_t sh = sizeof(float) * 3 *
+                        ((TZ + 2 * R) * (TY + 2 * R) * (TX + 2 * R) + (TZ + 2 * R) * (TY + 2 * R) * TX);
+  const dim3 g(total), blk(TZ * TY * TX);
+  switch (epi) {
+    case EPI_SMOOTH_MAX: k_gauss_cube_batch<R, TZ, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(E, owner); break;
+    case EPI_STORE_FINAL: k_gauss_cube_batch<R, TZ, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(E, owner); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gauss_cube_batch(const BatchEntry<GaussArgs>* E, const int* owner, int total, int radius, int epi,
+                            hipStream_t s) {
+  if (epi == EPI_COMPOSE_LDS) {
+    if (radius != 0) return hipErrorInvalidValue;
+    constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
+    constexpr size_t sh = sizeof(float) * 3 * (TZ + 2) * (TY + 2) * (TX + 2);
+    k_compose_cube_batch<TZ, TY, TX><<<dim3(total), dim3(TZ * TY * TX), sh, s>>>(E, owner);
+    return hipGetLastError();
+  }
+  switch (radius) {
+    case 0: return gauss_cube_batch_r<0>(E, owner, total, epi, s);
+    case 1: return gauss_cube_batch_r<1>(E, owner, total, epi, s);
+    case 2: return gauss_cube_batch_r<2>(E, owner, total, epi, s);
+    case 3: return gauss_cube_batch_r<3>(E, owner, total, epi, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 bool grad_tile_supported(int ty, int tx) { return (ty == 16 && tx == 32) || (ty == 8 && tx == 32); }
@@ -1855,6 +2115,44 @@ hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream
   if (t.cube) return grad_launch_cube(a, window, t, s);
   if (t.ty == 16 && t.tx == 32) return grad_launch_tile<16, 32>(a, window, t, s);
   if (t.ty == 8 && t.tx == 32) return grad_launch_tile<8, 32>(a, window, t, s);
+  return hipErrorInvalidValue;
+}
+
+bool grad_batch_supported(int window, const Tiling& t) {
+  if (t.cube) return grad_cube_supported(window);
+  return grad_tile_supported(t.ty, t.tx) && window >= 1 && window <= kMaxWindow && window % 2 == 1;
+}
+
+bool gauss_batch_supported(int radius, int epilogue, const Tiling& t) {
+  if (t.cube) return gauss_cube_supported(radius, epilogue);
+  if (!gauss_tile_supported(t.ty, t.tx) || radius < 0 || radius > kMaxRadius) return false;
+  if (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE_FINAL) return true;
+  return (epilogue == EPI_COMPOSE_LDS || epilogue == EPI_COMPOSE) && radius == 0;
+}
+
+hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
+                             const Tiling& t, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  if (t.cube) {
+    switch (window) {
+      case 1: return grad_cube_batch_w<1>(E, owner, total, s);
+      case 3: return grad_cube_batch_w<3>(E, owner, total, s);
+      case 5: return grad_cube_batch_w<5>(E, owner, total, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (t.ty == 16 && t.tx == 32) return grad_batch_tile<16, 32>(E, owner, total, window, s);
+  if (t.ty == 8 && t.tx == 32) return grad_batch_tile<8, 32>(E, owner, total, window, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gauss_batch(const BatchEntry<GaussArgs>* E, const int* owner, int total, int radius,
+                              int epilogue, const Tiling& t, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  if (t.cube) return gauss_cube_batch(E, owner, total, radius, epilogue, s);
+  if (t.ty == 16 && t.tx == 32) return gauss_batch_tile<16, 32>(E, owner, total, radius, epilogue, s);
+  if (t.ty == 8 && t.tx == 32) return gauss_batch_tile<8, 32>(E, owner, total, radius, epilogue, s);
+  if (t.ty == 8 && t.tx == 64) return gauss_batch_tile<8, 64>(E, owner, total, radius, epilogue, s);
   return hipErrorInvalidValue;
 }
 

@@ -208,15 +208,22 @@ fa_status drain_profile(fa_pair P) {
   return FA_OK;
 }
 
-fa_status launch_iteration(fa_pair P, const Level& L) {
-  const int w = P->p.cc_window;
-  fa_pair_s::Pending pe{};
-  pe.level = P->cur_level;
-  if (P->profiling) {
-    for (int k = 0; k < 5; ++k) FA_TRY(get_event(P, &pe.e[k]));
-    FA_HIP(hipEventRecord(pe.e[0], P->stream));
-  }
-  fa::GradArgs ga{};
+// The launches of one iteration of Algorithm 1 at level L: the fused
+// gradient (+ Adam), s = G_sigma_grad * a with M = max |s|, the composition
+// d' = u + d(x + u), and d = G_sigma_warp * d' with the loss record.
+struct IterPlan {
+  fa::GradArgs ga;
+  Tiling tg;
+  int window;
+  fa::GaussArgs g[3];
+  Tiling tgs[3];
+  int radius[3];
+  int epi[3];
+};
+
+void plan_iteration(fa_pair P, const Level& L, IterPlan& it) {
+  fa::GradArgs& ga = it.ga;
+  ga = fa::GradArgs{};
   ga.fixed = L.fixed;
   ga.moving_pad = L.moving_pad;
   ga.d = P->d;
@@ -239,11 +246,8 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   // use_jac: the kernel writes the Gateaux gradient, and a second launch turns
   // it into the Eulerian direction and applies Adam
   ga.mode = P->p.use_jac ? 1 : 0;
-  FA_HIP(fa::launch_grad(ga, w, L.tg, P->stream));
-  if (P->p.use_jac)
-    FA_HIP(fa::launch_eulerian_adam(P->a, P->d, P->m, P->v, P->ctl, L.shape.n0, L.shape.n1, L.shape.n2,
-                                    P->p.adam_beta1, P->p.adam_beta2, P->p.adam_eps, P->stream));
-  if (P->profiling) FA_HIP(hipEventRecord(pe.e[1], P->stream));
+  it.tg = L.tg;
+  it.window = P->p.cc_window;
 
   fa::GaussArgs gs{};
   gs.ctl = P->ctl;
@@ -253,19 +257,22 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   gs.eta = P->p.eta;
   gs.inv_n = (float)(1.0 / (double)L.n);
 
-  fa::GaussArgs g1 = gs;  // s = G * a into tmp, M = max |s|
+  fa::GaussArgs& g1 = it.g[0];  // s = G * a into tmp, M = max |s|
+  g1 = gs;
   g1.in = P->a;
   g1.out = P->tmp;
   g1.wts = P->wts + P->off_g;
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
-  FA_HIP(fa::launch_gauss(g1, P->rg, fa::EPI_SMOOTH_MAX, L.tsg, P->stream));
-  if (P->profiling) FA_HIP(hipEventRecord(pe.e[2], P->stream));
+  it.tgs[0] = L.tsg;
+  it.radius[0] = P->rg;
+  it.epi[0] = fa::EPI_SMOOTH_MAX;
 
   // d' = u + d(x + u) with u = -eta s / (2M), in place over s: the single-tap
   // launch reads s only at the voxel it writes, one plane ahead
-  fa::GaussArgs g2 = gs;
+  fa::GaussArgs& g2 = it.g[1];
+  g2 = gs;
   g2.in = P->tmp;
   g2.out = P->tmp;
   g2.d = P->d;
@@ -273,13 +280,14 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   g2.zc = L.tsc.zc;
   g2.tiles_y = L.tsc.tiles_y;
   g2.tiles_x = L.tsc.tiles_x;
+  it.tgs[1] = L.tsc;
+  it.radius[1] = 0;
   // |u| <= eta / 2: with eta <= 2 the sample stays within one voxel, and d
   // is staged in LDS instead of gathered
-  const int epi_c = P->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE;
-  FA_HIP(fa::launch_gauss(g2, 0, epi_c, L.tsc, P->stream));
-  if (P->profiling) FA_HIP(hipEventRecord(pe.e[3], P->stream));
+  it.epi[1] = P->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE;
 
-  fa::GaussArgs g3 = gs;  // d = G * d'; record loss, advance t
+  fa::GaussArgs& g3 = it.g[2];  // d = G * d'; record loss, advance t
+  g3 = gs;
   g3.in = P->tmp;
   g3.out = P->d;
   g3.wts = P->wts + P->off_w;
@@ -290,9 +298,34 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
   g3.n_partials = L.tg.blocks();
   g3.loss_hist = P->loss_hist;
   g3.loss_cap = P->loss_cap;
-  FA_HIP(fa::launch_gauss(g3, P->rw, fa::EPI_STORE_FINAL, L.tsw, P->stream));
+  it.tgs[2] = L.tsw;
+  it.radius[2] = P->rw;
+  it.epi[2] = fa::EPI_STORE_FINAL;
+}
+
+fa_status launch_eulerian(fa_pair P, const Level& L) {
+  FA_HIP(fa::launch_eulerian_adam(P->a, P->d, P->m, P->v, P->ctl, L.shape.n0, L.shape.n1, L.shape.n2,
+                                  P->p.adam_beta1, P->p.adam_beta2, P->p.adam_eps, P->stream));
+  return FA_OK;
+}
+
+fa_status launch_iteration(fa_pair P, const Level& L) {
+  fa_pair_s::Pending pe{};
+  pe.level = P->cur_level;
   if (P->profiling) {
-    FA_HIP(hipEventRecord(pe.e[4], P->stream));
+    for (int k = 0; k < 5; ++k) FA_TRY(get_event(P, &pe.e[k]));
+    FA_HIP(hipEventRecord(pe.e[0], P->stream));
+  }
+  IterPlan it;
+  plan_iteration(P, L, it);
+  FA_HIP(fa::launch_grad(it.ga, it.window, it.tg, P->stream));
+  if (P->p.use_jac) FA_TRY(launch_eulerian(P, L));
+  if (P->profiling) FA_HIP(hipEventRecord(pe.e[1], P->stream));
+  for (int k = 0; k < 3; ++k) {
+    FA_HIP(fa::launch_gauss(it.g[k], it.radius[k], it.epi[k], it.tgs[k], P->stream));
+    if (P->profiling) FA_HIP(hipEventRecord(pe.e[2 + k], P->stream));
+  }
+  if (P->profiling) {
     P->pending.push_back(pe);
     if (P->pending.size() >= 4096) FA_TRY(drain_profile(P));
   }
@@ -337,6 +370,247 @@ fa_status advance_levels(fa_pair P) {
 
 bool schedule_done(const fa_pair P) {
   return P->cur_level == (int)P->levels.size() - 1 && P->cur_iter >= P->levels.back().iters;
+}
+
+// ---- batched launches -------------------------------------------------------
+// One iteration of several pairs as one launch per kernel and launch form: the
+// entries of a launch are the pairs whose kernel shares the template
+// parameters (gradient: window and tiling form; smoothing and composition:
+// radius, epilogue and tiling form).  The tables of all launches live in one
+// device buffer, uploaded again only when the batch's composition changes (a
+// level transition or a finished pair): every value that changes from one
+// iteration to the next is in the pairs' control blocks on the device.
+struct BatchLaunch {
+  int stage;       // 0: gradient; 1, 2, 3: the three launches that follow it
+  Tiling t;        // tile shape and form shared by the entries
+  int param;       // window (stage 0) or Gaussian radius
+  int epi;         // epilogue (stages 1 to 3)
+  size_t ent_off;  // byte offsets of the entries and the owner array
+  size_t own_off;
+  int total;       // workgroups of the launch
+};
+
+struct BatchTables {
+  std::vector<BatchLaunch> launches;
+  std::vector<unsigned char> host;
+  std::vector<int> jac;   // live pairs with use_jac (their Eulerian launch follows stage 0)
+  void* dev = nullptr;
+  size_t dev_cap = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <class Args>
+void append_launch(BatchTables& bt, int stage, const Tiling& t, int param, int epi,
+                   const std::vector<const Args*>& args, const std::vector<int>& nblocks) {
+  using E = fa::BatchEntry<Args>;
+  BatchLaunch bl{stage, t, param, epi, 0, 0, 0};
+  for (int nb : nblocks) bl.total += nb;
+  bl.ent_off = align256(bt.host.size());
+  bl.own_off = align256(bl.ent_off + args.size() * sizeof(E));
+  bt.host.resize(bl.own_off + (size_t)bl.total * sizeof(int));
+  int first = 0;
+  for (size_t e = 0; e < args.size(); ++e) {
+    E en;
+    en.a = *args[e];
+    en.first = first;
+    en.nblocks = nblocks[e];
+    std::memcpy(bt.host.data() + bl.ent_off + e * sizeof(E), &en, sizeof(E));
+    for (int k = 0; k < en.nblocks; ++k) {
+      const int v = (int)e;
+      std::memcpy(bt.host.data() + bl.own_off + (size_t)(first + k) * sizeof(int), &v, sizeof(int));
+    }
+    first += en.nblocks;
+  }
+  bt.launches.push_back(bl);
+}
+
+fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) {
+  bt.launches.clear();
+  bt.host.clear();
+  bt.jac.clear();
+  const size_t n = live.size();
+  std::vector<IterPlan> its(n);
+  for (size_t i = 0; i < n; ++i) {
+    plan_iteration(live[i], live[i]->levels[live[i]->cur_level], its[i]);
+    if (live[i]->p.use_jac) bt.jac.push_back((int)i);
+  }
+  auto same_form = [](const Tiling& a, const Tiling& b) {
+    return a.cube == b.cube && (a.cube || (a.ty == b.ty && a.tx == b.tx));
+  };
+  // stage 0: the gradient, grouped by window and tiling form
+  std::vector<char> taken(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    if (taken[i]) continue;
+    std::vector<size_t> mem;
+    for (size_t j = i; j < n; ++j) {
+      if (taken[j] || its[j].window != its[i].window || !same_form(its[j].tg, its[i].tg)) continue;
+      taken[j] = 1;
+      mem.push_back(j);
+    }
+    if (!fa::grad_batch_supported(its[i].window, its[i].tg))
+      return fail(FA_EINVAL, "no batched gradient launch for this window and tiling");
+    std::vector<Tiling*> ts;
+    std::vector<int> n0s;
+    std::vector<char> pinned;
+    for (size_t j : mem) {
+      ts.push_back(&its[j].tg);
+      n0s.push_back(its[j].ga.n0);
+      pinned.push_back(live[j]->tune[fa::KIND_GRAD].zc > 0);
+    }
+    std::vector<Tiling> orig;
+    for (size_t j : mem) orig.push_back(its[j].tg);
+    fa::batch_chunks(fa::KIND_GRAD, 4 * (its[i].window / 2), ts, n0s, pinned);
+    std::vector<const fa::GradArgs*> args;
+    std::vector<int> nb;
+    for (size_t q = 0; q < mem.size(); ++q) {
+      const size_t j = mem[q];
+      // one loss partial per workgroup: stay within the pair's partials buffer
+      if (its[j].tg.blocks() > live[j]->partials_cap) its[j].tg = orig[q];
+      its[j].ga.zc = its[j].tg.zc;
+      its[j].g[2].n_partials = its[j].tg.blocks();   // the loss record sums every gradient workgroup
+      args.push_back(&its[j].ga);
+      nb.push_back(its[j].tg.blocks());
+    }
+    append_launch(bt, 0, its[i].tg, its[i].window, 0, args, nb);
+  }
+  // stages 1 to 3, grouped by radius, epilogue and tiling form
+  static const fa::KernelKind kinds[3] = {fa::KIND_SMOOTH_MAX, fa::KIND_COMPOSE, fa::KIND_WARP_SMOOTH};
+  for (int k = 0; k < 3; ++k) {
+    std::fill(taken.begin(), taken.end(), 0);
+    for (size_t i = 0; i < n; ++i) {
+      if (taken[i]) continue;
+      std::vector<size_t> mem;
+      for (size_t j = i; j < n; ++j) {
+        if (taken[j] || its[j].radius[k] != its[i].radius[k] || its[j].epi[k] != its[i].epi[k] ||
+            !same_form(its[j].tgs[k], its[i].tgs[k]))
+          continue;
+        taken[j] = 1;
+        mem.push_back(j);
+      }
+      if (!fa::gauss_batch_supported(its[i].radius[k], its[i].epi[k], its[i].tgs[k]))
+        return fail(FA_EINVAL, "no batched smoothing launch for this radius, epilogue and tiling");
+      std::vector<Tiling*> ts;
+      std::vector<int> n0s;
+      std::vector<char> pinned;
+      for (size_t j : mem) {
+        ts.push_back(&its[j].tgs[k]);
+        n0s.push_back(its[j].g[k].n0);
+        pinned.push_back(live[j]->tune[kinds[k]].zc > 0);
+      }
+      // halo planes: 2R of the smoothing, one plane ahead for the composition
+      fa::batch_chunks(kinds[k], k == 1 ? 2 : 2 * its[i].radius[k], ts, n0s, pinned);
+      std::vector<const fa::GaussArgs*> args;
+      std::vector<int> nb;
+      for (size_t j : mem) {
+        its[j].g[k].zc = its[j].tgs[k].zc;
+        args.push_back(&its[j].g[k]);
+        nb.push_back(its[j].tgs[k].blocks());
+      }
+      append_launch(bt, k + 1, its[i].tgs[k], its[i].radius[k], its[i].epi[k], args, nb);
+    }
+  }
+  return FA_OK;
+}
+
+// Copies the host image to the device.  Synchronises: the launches already
+// queued read the previous tables, and the host image may change after this.
+fa_status upload_batch_tables(BatchTables& bt, hipStream_t s) {
+  const size_t need = std::max<size_t>(bt.host.size(), 256);
+  FA_HIP(hipStreamSynchronize(s));
+  if (need > bt.dev_cap) {
+    if (bt.dev) FA_HIP(hipFree(bt.dev));
+    bt.dev = nullptr;
+    bt.dev_cap = 0;
+    FA_TRY(dalloc((unsigned char**)&bt.dev, need, "batch tables"));
+    bt.dev_cap = need;
+  }
+  if (!bt.host.empty())
+    FA_HIP(hipMemcpyAsync(bt.dev, bt.host.data(), bt.host.size(), hipMemcpyHostToDevice, s));
+  FA_HIP(hipStreamSynchronize(s));
+  return FA_OK;
+}
+
+fa_status launch_batch_iteration(const std::vector<fa_pair>& live, const BatchTables& bt, hipStream_t s) {
+  const unsigned char* base = static_cast<const unsigned char*>(bt.dev);
+  bool jac_done = false;
+  for (const BatchLaunch& bl : bt.launches) {
+    if (bl.stage >= 1 && !jac_done) {
+      for (int j : bt.jac) FA_TRY(launch_eulerian(live[j], live[j]->levels[live[j]->cur_level]));
+      jac_done = true;
+    }
+    const int* own = reinterpret_cast<const int*>(base + bl.own_off);
+    if (bl.stage == 0) {
+      const auto* E = reinterpret_cast<const fa::BatchEntry<fa::GradArgs>*>(base + bl.ent_off);
+      FA_HIP(fa::launch_grad_batch(E, own, bl.total, bl.param, bl.t, s));
+    } else {
+      const auto* E = reinterpret_cast<const fa::BatchEntry<fa::GaussArgs>*>(base + bl.ent_off);
+      FA_HIP(fa::launch_gauss_batch(E, own, bl.total, bl.param, bl.epi, bl.t, s));
+    }
+  }
+  return FA_OK;
+}
+
+fa_status check_batch(fa_pair* pairs, int n, int max_iters) {
+  if (n < 0 || (n > 0 && !pairs)) return fail(FA_EINVAL, "pairs is NULL or n < 0");
+  if (max_iters < 0) return fail(FA_EINVAL, "max_iters must be >= 0");
+  for (int i = 0; i < n; ++i) {
+    if (!pairs[i]) return fail(FA_EINVAL, "pairs[" + std::to_string(i) + "] is NULL");
+    if (!pairs[i]->scheduled) return fail(FA_ESTATE, "pairs[" + std::to_string(i) + "] has no schedule");
+    for (int j = 0; j < i; ++j)
+      if (pairs[j] == pairs[i]) return fail(FA_EINVAL, "a pair appears twice");
+  }
+  return FA_OK;
+}
+
+int count_finished(fa_pair* pairs, int n) {
+  int f = 0;
+  for (int i = 0; i < n; ++i) f += schedule_done(pairs[i]) ? 1 : 0;
+  return f;
+}
+
+// The fused batch proper, with every pair's work on stream s.
+fa_status run_batch_fused(fa_pair* pairs, int n, int max_iters, hipStream_t s) {
+  BatchTables bt;
+  std::vector<char> alive(n, 1);
+  std::vector<std::pair<int, int>> sig, last;
+  std::vector<fa_pair> live;
+  fa_status st = FA_OK;
+  for (int k = 0; k < max_iters && st == FA_OK; ++k) {
+    live.clear();
+    sig.clear();
+    for (int i = 0; i < n && st == FA_OK; ++i) {
+      if (!alive[i]) continue;
+      st = advance_levels(pairs[i]);
+      if (st != FA_OK) break;
+      if (schedule_done(pairs[i])) {
+        alive[i] = 0;
+        continue;
+      }
+      live.push_back(pairs[i]);
+      sig.emplace_back(i, pairs[i]->cur_level);
+    }
+    if (st != FA_OK || live.empty()) break;
+    if (sig != last) {
+      if ((st = build_batch_tables(live, bt)) != FA_OK) break;
+      if ((st = upload_batch_tables(bt, s)) != FA_OK) break;
+      last = sig;
+    }
+    if ((st = launch_batch_iteration(live, bt, s)) != FA_OK) break;
+    for (fa_pair P : live) {
+      P->cur_iter += 1;
+      P->t_done += 1;
+      P->iters_done += 1;
+    }
+  }
+  if (bt.dev) {
+    // the queued launches read the tables
+    const hipError_t e1 = hipStreamSynchronize(s);
+    const hipError_t e2 = hipFree(bt.dev);
+    if (st == FA_OK && e1 != hipSuccess) st = fail(FA_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e1));
+    if (st == FA_OK && e2 != hipSuccess) st = fail(FA_EHIP, std::string("hipFree: ") + hipGetErrorString(e2));
+  }
+  return st;
 }
 
 }  // namespace
@@ -410,6 +684,46 @@ Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu, bool 
   t.zc = zc;
   t.chunks = (s.n0 + zc - 1) / zc;
   return t;
+}
+
+// Chunk lengths along n0 for a batched march launch, whose entries share the
+// GPU's resident workgroup slots.  Cost model: rounds of resident workgroups
+// (ceil(workgroups / slots)) times the plane steps of one chunk (its planes
+// plus the halo planes it recomputes); the common chunk that minimises it,
+// then evened out per entry (the same number of chunks, each as short as that
+// allows).  A launch of one entry keeps choose_tiling's chunk (the longest
+// that keeps the launch within the resident slots, which the model also
+// favours).  Entries with a chunk set by fa_pair_set_tuning keep it.
+void batch_chunks(KernelKind kind, int halo, const std::vector<Tiling*>& ts, const std::vector<int>& n0s,
+                  const std::vector<char>& pinned) {
+  static const int kSlots[4] = {512, 1024, 512, 512};
+  static const int kMinChunk[4] = {1, 4, 4, 1};
+  if (ts.size() < 2 || ts[0]->cube) return;
+  int zmax = 1;
+  for (size_t i = 0; i < ts.size(); ++i) zmax = std::max(zmax, n0s[i]);
+  double best = 0.0;
+  int best_zc = 0;
+  for (int zc = kMinChunk[kind]; zc <= std::max(zmax, kMinChunk[kind]); ++zc) {
+    int64_t blocks = 0;
+    int steps = 0;
+    for (size_t i = 0; i < ts.size(); ++i) {
+      const int z = pinned[i] ? ts[i]->zc : std::min(zc, n0s[i]);
+      blocks += (int64_t)ts[i]->tiles_y * ts[i]->tiles_x * ((n0s[i] + z - 1) / z);
+      steps = std::max(steps, z + halo);
+    }
+    const double cost = (double)((blocks + kSlots[kind] - 1) / kSlots[kind]) * steps;
+    if (best_zc == 0 || cost < best) {
+      best = cost;
+      best_zc = zc;
+    }
+  }
+  for (size_t i = 0; i < ts.size(); ++i) {
+    if (pinned[i]) continue;
+    const int z = std::min(best_zc, n0s[i]);
+    const int chunks = (n0s[i] + z - 1) / z;
+    ts[i]->zc = (n0s[i] + chunks - 1) / chunks;
+    ts[i]->chunks = (n0s[i] + ts[i]->zc - 1) / ts[i]->zc;
+  }
 }
 
 }  // namespace fa
@@ -621,14 +935,7 @@ fa_status fa_pair_step(fa_pair P, int max_iters, int* iters_done, int* finished)
 
 fa_status fa_batch_step(fa_pair* pairs, int n, int max_iters, int* n_finished) {
   if (n_finished) *n_finished = 0;
-  if (n < 0 || (n > 0 && !pairs)) return fail(FA_EINVAL, "pairs is NULL or n < 0");
-  if (max_iters < 0) return fail(FA_EINVAL, "max_iters must be >= 0");
-  for (int i = 0; i < n; ++i) {
-    if (!pairs[i]) return fail(FA_EINVAL, "pairs[" + std::to_string(i) + "] is NULL");
-    if (!pairs[i]->scheduled) return fail(FA_ESTATE, "pairs[" + std::to_string(i) + "] has no schedule");
-    for (int j = 0; j < i; ++j)
-      if (pairs[j] == pairs[i]) return fail(FA_EINVAL, "a pair appears twice");
-  }
+  FA_TRY(check_batch(pairs, n, max_iters));
   // one iteration per pair in turn: each stream always has work queued
   std::vector<char> live(n, 1);
   for (int k = 0; k < max_iters; ++k) {
@@ -642,11 +949,51 @@ fa_status fa_batch_step(fa_pair* pairs, int n, int max_iters, int* n_finished) {
     }
     if (active == 0) break;
   }
-  if (n_finished) {
-    int f = 0;
-    for (int i = 0; i < n; ++i) f += schedule_done(pairs[i]) ? 1 : 0;
-    *n_finished = f;
+  if (n_finished) *n_finished = count_finished(pairs, n);
+  return FA_OK;
+}
+
+fa_status fa_batch_step_fused(fa_pair* pairs, int n, int max_iters, int* n_finished) {
+  if (n_finished) *n_finished = 0;
+  FA_TRY(check_batch(pairs, n, max_iters));
+  for (int i = 1; i < n; ++i)
+    if (pairs[i]->device != pairs[0]->device) return fail(FA_EINVAL, "the pairs of a batch must share a device");
+  if (n > 0 && max_iters > 0) {
+    // Every pair's work goes to pairs[0]'s stream for the duration of the
+    // call; the stream first waits for the others' queued work, and they
+    // wait for it at the end.
+    const hipStream_t s = pairs[0]->stream;
+    std::vector<hipStream_t> saved(n);
+    std::vector<hipEvent_t> evs;
+    fa_status st = FA_OK;
+    for (int i = 0; i < n && st == FA_OK; ++i) {
+      saved[i] = pairs[i]->stream;
+      if (saved[i] == s) continue;
+      hipEvent_t e = nullptr;
+      hipError_t he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (he == hipSuccess) {
+        evs.push_back(e);
+        he = hipEventRecord(e, saved[i]);
+      }
+      if (he == hipSuccess) he = hipStreamWaitEvent(s, e, 0);
+      if (he != hipSuccess) st = fail(FA_EHIP, std::string("joining the pairs' streams: ") + hipGetErrorString(he));
+    }
+    if (st == FA_OK) {
+      for (int i = 0; i < n; ++i) pairs[i]->stream = s;
+      st = run_batch_fused(pairs, n, max_iters, s);
+      for (int i = 0; i < n; ++i) pairs[i]->stream = saved[i];
+    }
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
+      evs.push_back(done);
+      if (hipEventRecord(done, s) == hipSuccess)
+        for (int i = 0; i < n; ++i)
+          if (saved[i] != s) (void)hipStreamWaitEvent(saved[i], done, 0);
+    }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (st != FA_OK) return st;
   }
+  if (n_finished) *n_finished = count_finished(pairs, n);
   return FA_OK;
 }
 
@@ -790,6 +1137,28 @@ fa_status fa_pair_get_level_image(fa_pair P, int level, int which, float* dev_ou
   if (!dev_out) return FA_OK;
   FA_HIP(hipMemcpyAsync(dev_out, which ? L.moving : L.fixed, (size_t)L.n * sizeof(float),
                         hipMemcpyDeviceToDevice, P->stream));
+  return FA_OK;
+}
+
+fa_status fa_plan_tiling(int kind, int n, const fa_shape* shapes, int halo, int batched, int* zc_out,
+                         int* blocks_out) {
+  if (kind < 0 || kind > 3) return fail(FA_EINVAL, "kind must be in [0, 3]");
+  if (n < 1 || !shapes) return fail(FA_EINVAL, "shapes is NULL or n < 1");
+  if (halo < 0) return fail(FA_EINVAL, "halo must be >= 0");
+  std::vector<Tiling> ts(n);
+  std::vector<Tiling*> tp(n);
+  std::vector<int> n0s(n);
+  for (int i = 0; i < n; ++i) {
+    FA_TRY(check_shape(shapes[i]));
+    ts[i] = choose_tiling(shapes[i], (fa::KernelKind)kind);
+    tp[i] = &ts[i];
+    n0s[i] = shapes[i].n0;
+  }
+  if (batched) fa::batch_chunks((fa::KernelKind)kind, halo, tp, n0s, std::vector<char>(n, 0));
+  for (int i = 0; i < n; ++i) {
+    if (zc_out) zc_out[i] = ts[i].zc;
+    if (blocks_out) blocks_out[i] = ts[i].blocks();
+  }
   return FA_OK;
 }
 

@@ -68,6 +68,8 @@ SIGNATURES = {
     "fa_pair_set_tuning": (_I, [_P, _I, _I, _I, _I, _I]),
     "fa_pair_get_profile": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_double), _IP]),
     "fa_batch_step": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
+    "fa_batch_step_fused": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
+    "fa_plan_tiling": (_I, [_I, _I, ctypes.POINTER(fa_shape), _I, _I, _IP, _IP]),
     "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
     "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "fa_lncc_destroy": (None, [_P]),
@@ -298,4 +300,22 @@ def fa_batch_step(pairs, max_iters: int) -> int:
     arr = (_P * len(pairs))(*pairs)
     fin = ctypes.c_int(0)
     _check(load_library().fa_batch_step(arr, len(pairs), int(max_iters), ctypes.byref(fin)))
+    return fin.value
+
+
+def fa_plan_tiling(kind: int, shapes, halo: int, batched: bool):
+    """Automatic march chunks (planes per workgroup) and workgroup counts for
+    volumes of the given shapes: each alone, or in one batched launch."""
+    n = len(shapes)
+    arr = (fa_shape * n)(*[fa_shape(*map(int, s)) for s in shapes])
+    zc = (ctypes.c_int * n)()
+    nb = (ctypes.c_int * n)()
+    _check(load_library().fa_plan_tiling(int(kind), n, arr, int(halo), int(bool(batched)), zc, nb))
+    return list(zc), list(nb)
+
+
+def fa_batch_step_fused(pairs, max_iters: int) -> int:
+    arr = (_P * len(pairs))(*pairs)
+    fin = ctypes.c_int(0)
+    _check(load_library().fa_batch_step_fused(arr, len(pairs), int(max_iters), ctypes.byref(fin)))
     return fin.value

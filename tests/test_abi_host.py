@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2404_01249_amd import fa
@@ -73,10 +74,63 @@ def test_null_pointers_rejected(lib):
     lib.fa_pair_destroy(None)
 
 
-def test_batch_step_rejects_bad_arguments(lib):
+@pytest.mark.parametrize("name", ["fa_batch_step", "fa_batch_step_fused"])
+def test_batch_step_rejects_bad_arguments(lib, name):
+    fn = getattr(lib, name)
     fin = ctypes.c_int(7)
-    assert lib.fa_batch_step(None, 0, 1, ctypes.byref(fin)) == fa.FA_OK and fin.value == 0
-    assert lib.fa_batch_step(None, 2, 1, None) == fa.FA_EINVAL
+    assert fn(None, 0, 1, ctypes.byref(fin)) == fa.FA_OK and fin.value == 0
+    assert fn(None, 2, 1, None) == fa.FA_EINVAL
     arr = (ctypes.c_void_p * 1)(None)
-    assert lib.fa_batch_step(arr, 1, 1, None) == fa.FA_EINVAL
-    assert lib.fa_batch_step(arr, 1, -1, None) == fa.FA_EINVAL
+    assert fn(arr, 1, 1, None) == fa.FA_EINVAL
+    assert fn(arr, 1, -1, None) == fa.FA_EINVAL
+
+
+def test_plan_tiling_single_volumes():
+    """The automatic march chunks of one registration's launches: the
+    longest chunk that keeps the launch within the resident workgroups
+    (512 for the gradient kernel, 1024 for the sigma_grad smoothing)."""
+    assert fa.fa_plan_tiling(0, [(160, 192, 224)], 8, False) == ([27], [504])
+    assert fa.fa_plan_tiling(0, [(80, 96, 112)], 8, False) == ([4], [480])
+    assert fa.fa_plan_tiling(1, [(160, 192, 224)], 6, False) == ([14], [1008])
+    # smoothing chunks are at least 4 planes (their halo is 2R planes)
+    assert fa.fa_plan_tiling(1, [(40, 48, 56)], 6, False) == ([4], [60])
+
+
+def test_plan_tiling_batched_chunks_cover_every_volume():
+    rng = np.random.default_rng(5)
+    for trial in range(60):
+        kind = int(rng.integers(0, 4))
+        n = int(rng.integers(1, 9))
+        shapes = [tuple(int(v) for v in rng.integers(2, 260, 3)) for _ in range(n)]
+        halo = int(rng.integers(0, 13))
+        zs, bs = fa.fa_plan_tiling(kind, shapes, halo, False)
+        zb, bb = fa.fa_plan_tiling(kind, shapes, halo, True)
+        if n == 1:
+            assert (zb, bb) == (zs, bs)   # a launch of one keeps its own chunk
+        for (n0, n1, n2), z, b in zip(shapes, zb, bb):
+            ty = 16 if n1 >= 16 else 8
+            tiles = -(-n1 // ty) * -(-n2 // 32)
+            chunks = -(-n0 // z)
+            assert 1 <= z <= n0
+            assert (chunks - 1) * z < n0 <= chunks * z
+            assert b == tiles * chunks
+
+
+def test_plan_tiling_batch_lengthens_chunks():
+    """Four 80x96x112 volumes share the 512 resident gradient workgroups:
+    16-plane chunks (a third of the halo recomputation of 4-plane ones) fill
+    them in one round."""
+    zc, nb = fa.fa_plan_tiling(0, [(80, 96, 112)] * 4, 8, True)
+    assert zc == [16] * 4 and nb == [120] * 4
+    zc, nb = fa.fa_plan_tiling(0, [(160, 192, 224)] * 4, 8, True)
+    assert zc == [54] * 4 and sum(nb) == 1008
+
+
+def test_plan_tiling_rejects_bad_arguments(lib):
+    arr = (fa.fa_shape * 1)(fa.fa_shape(10, 10, 10))
+    assert lib.fa_plan_tiling(4, 1, arr, 0, 0, None, None) == fa.FA_EINVAL
+    assert lib.fa_plan_tiling(0, 0, arr, 0, 0, None, None) == fa.FA_EINVAL
+    assert lib.fa_plan_tiling(0, 1, None, 0, 0, None, None) == fa.FA_EINVAL
+    assert lib.fa_plan_tiling(0, 1, arr, -1, 0, None, None) == fa.FA_EINVAL
+    bad = (fa.fa_shape * 1)(fa.fa_shape(1, 10, 10))
+    assert lib.fa_plan_tiling(0, 1, bad, 0, 0, None, None) == fa.FA_ESHAPE

@@ -336,9 +336,11 @@ def test_runs_are_bitwise_deterministic():
     assert np.array_equal(hist[0][1], hist[1][1])
 
 
-def test_batched_pairs_on_separate_streams_match_single_runs():
-    """Several registrations advanced together on their own streams give the
-    results of each run alone (bitwise: the same kernels on the same data)."""
+@pytest.mark.parametrize("fused", [False, True], ids=["streams", "fused"])
+def test_batched_pairs_match_single_runs(fused):
+    """Several registrations advanced together, on their own streams or by
+    batched launches, give the results of each run alone (bitwise: the same
+    kernel bodies on the same data)."""
     from paper_2404_01249_amd import run_batch
     fixed, moving, _ = make_problem((21, 37, 45), seed=72)
     settings = [dict(eta=0.25), dict(eta=1.0, sigma_warp=0.0), dict(eta=2.0, use_jac=True)]
@@ -353,12 +355,62 @@ def test_batched_pairs_on_separate_streams_match_single_runs():
     pairs = [Pair(dev(fixed), dev(moving), stream=st, **kw) for st, kw in zip(streams, settings)]
     for pr in pairs:
         pr.set_schedule([2.0, 1.0], [5, 4])
-    assert run_batch(pairs) == len(pairs)
+    assert run_batch(pairs, fused=fused) == len(pairs)
     for pr, (loss, field) in zip(pairs, ref):
-        assert np.array_equal(pr.loss_history(), loss)
+        if fused:   # the loss partials may be grouped by other chunks
+            np.testing.assert_allclose(pr.loss_history(), loss, rtol=1e-6, atol=0)
+        else:
+            assert np.array_equal(pr.loss_history(), loss)
         got = pr.field()
         pr.stream.synchronize()
         assert np.array_equal(host(got), field)
+        pr.close()
+
+
+def test_fused_batch_of_uneven_pairs_matches_single_runs():
+    """Batched launches over pairs that differ in size (brick and march
+    launches, 16x32 and 8x32 tiles), window, step size (eta = 3 takes the
+    composition with gathers), smoothing, schedule and use_jac, advanced a few
+    iterations per call so that the launch tables change as pairs change
+    level or finish: every pair gives the field of its run alone, bitwise
+    (each voxel's arithmetic does not depend on the launch shape)."""
+    from paper_2404_01249_amd import run_batch
+    problems = [make_problem((21, 37, 45), seed=73), make_problem((40, 48, 56), seed=74),
+                make_problem((30, 12, 50), seed=75)]
+    cfgs = [(0, dict(eta=0.5), [2.0, 1.0], [5, 4]),
+            (1, dict(eta=3.0), [2.0, 1.0], [3, 6]),
+            (1, dict(eta=1.0, window=3), [1.0], [7]),
+            (2, dict(eta=0.25, use_jac=True), [2.0, 1.0], [4, 2]),
+            (0, dict(eta=2.0, sigma_warp=0.0), [4.0, 2.0, 1.0], [2, 3, 2]),
+            (1, dict(eta=0.5, window=7, sigma_grad=1.5), [2.0, 1.0], [2, 3]),
+            (2, dict(eta=1.0), [1.0], [9])]
+    ref = []
+    for k, kw, sc, it in cfgs:
+        fixed, moving, _ = problems[k]
+        pr = new_pair(fixed, moving, **kw)
+        pr.set_schedule(sc, it)
+        pr.run()
+        ref.append((pr.loss_history(), host(pr.field())))
+        pr.close()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    pairs = []
+    for i, (k, kw, sc, it) in enumerate(cfgs):
+        fixed, moving, _ = problems[k]
+        pr = Pair(dev(fixed), dev(moving), stream=streams[i % 3] if i % 2 else None, **kw)
+        pr.set_schedule(sc, it)
+        pairs.append(pr)
+    calls, fin = 0, 0
+    while fin < len(pairs):
+        fin = run_batch(pairs, 3, fused=True)
+        calls += 1
+        assert calls <= 10
+    for i, (pr, (loss, field)) in enumerate(zip(pairs, ref)):
+        # a batched launch may chunk the march differently, which regroups
+        # the loss partials (summed in double, then rounded to float)
+        np.testing.assert_allclose(pr.loss_history(), loss, rtol=1e-6, atol=0)
+        got = pr.field()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(got), field), i
         pr.close()
 
 
