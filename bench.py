@@ -19,6 +19,9 @@ Prints one JSON line.  Besides the headline value it reports
   the paper's grid search) advanced together, on separate streams and by
   batched launches (one launch per kernel for all of them), against the same
   registrations run one after another;
+* ``grid_search``: a hyperparameter grid search as one fused batch: pairs of
+  three sizes, each at four step sizes (96 registrations), against the same
+  registrations run one after another;
 * ``use_jac``: the same registration with Algorithm 1's use_jac on (the
   Eulerian direction J(phi)^T dU/dphi), its time relative to the default
   Jacobian-free form, and its accuracy;
@@ -33,6 +36,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -192,6 +197,61 @@ def run_batch_compare(p, k, params):
     return out
 
 
+def run_grid_search(n_variants, params, sequential_too=True):
+    """The grid-search batch: pairs of three sizes (96^3, 128x160x128,
+    160x192x224; blob volumes as in the 64^3 workload, blob widths scaled to
+    the size), each registered at four step sizes (eta 0.25, 0.5, 1, 2) over
+    scales 2, 1 at 100, 50 iterations.  One pair is generated per size; its
+    n_variants variants are the pair flipped along subsets of the axes
+    (distinct pairs with the same statistics).  Returns the seconds of the
+    registrations run one after another and as one fused batch, and the
+    voxel-iterations of the batch."""
+    import torch
+
+    from paper_2404_01249_amd import Pair, run_batch, synth
+    etas = [0.25, 0.5, 1.0, 2.0]
+    scales, iters = [2.0, 1.0], [100, 50]
+    base = {k: v for k, v in params.items() if k != "eta"}
+    pairs, vox_iters = [], 0
+    for k, shp in enumerate([(96, 96, 96), (128, 160, 128), (160, 192, 224)]):
+        sp = synth.blobs_pair(shp, seed=400 + k, n_blobs=20, sigma_range=(4.0 * min(shp) / 64, 8.0 * min(shp) / 64),
+                              field_sigma=6.0, field_max=3.0)
+        f0 = torch.from_numpy(sp.fixed).cuda()
+        m0 = torch.from_numpy(sp.moving).cuda()
+        for v in range(n_variants):
+            axes = [a for a in range(3) if (v >> a) & 1]
+            f = torch.flip(f0, axes).contiguous() if axes else f0
+            m = torch.flip(m0, axes).contiguous() if axes else m0
+            for e in etas:
+                pairs.append(Pair(f, m, eta=e, **base))
+                vox_iters += sum(int(np.prod([int(np.floor(n / s + 0.5)) for n in shp])) * it
+                                 for s, it in zip(scales, iters))
+    torch.cuda.synchronize()
+
+    def sequential():
+        for pr in pairs:
+            pr.set_schedule(scales, iters)
+            pr.run()
+        torch.cuda.synchronize()
+
+    def fused():
+        for pr in pairs:
+            pr.set_schedule(scales, iters)
+        run_batch(pairs, fused=True)
+        torch.cuda.synchronize()
+
+    out = {"registrations": len(pairs), "voxel_iters": vox_iters}
+    forms = (("sequential", sequential), ("fused", fused)) if sequential_too else (("fused", fused),)
+    for name, fn in forms:
+        fn()
+        t0 = time.perf_counter()
+        fn()
+        out[name] = time.perf_counter() - t0
+    for pr in pairs:
+        pr.close()
+    return out
+
+
 def run_plain(p, steps, warmup, params):
     import torch
 
@@ -264,6 +324,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4,
                     help="registrations run together (streams, then batched launches) for the batch figure (0 skips)")
+    ap.add_argument("--grid", type=int, default=8,
+                    help="variants per size in the grid-search batch (8 gives 96 registrations; 0 skips)")
+    ap.add_argument("--grid-fused-only", action="store_true",
+                    help="grid-search batch: skip the sequential comparison (for kernel traces)")
     ap.add_argument("--jac-steps", type=int, default=2,
                     help="registrations timed with use_jac on (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
@@ -349,6 +413,18 @@ def main():
                         "fused_voxel_iters_per_s": nb * vox_iters / bt["fused"],
                         "streams_speedup": bt["sequential"] / bt["batched"],
                         "fused_speedup": bt["sequential"] / bt["fused"]}
+    if args.grid > 0:
+        g = run_grid_search(min(args.grid, 8), params, not args.grid_fused_only)
+        out["grid_search"] = {
+            "registrations": g["registrations"],
+            "sizes": ["96x96x96", "128x160x128", "160x192x224"], "etas": [0.25, 0.5, 1.0, 2.0],
+            "schedule": "scales [2.0, 1.0] at [100, 50]", "voxel_iters": g["voxel_iters"],
+            "fused_s": g["fused"], "fused_voxel_iters_per_s": g["voxel_iters"] / g["fused"]}
+        if "sequential" in g:
+            out["grid_search"].update({
+                "sequential_s": g["sequential"],
+                "sequential_voxel_iters_per_s": g["voxel_iters"] / g["sequential"],
+                "fused_speedup": g["sequential"] / g["fused"]})
     if args.jac_steps > 0:
         jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
         out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}
