@@ -22,6 +22,9 @@ Prints one JSON line.  Besides the headline value it reports
 * ``grid_search``: a hyperparameter grid search as one fused batch: pairs of
   three sizes, each at four step sizes (96 registrations), against the same
   registrations run one after another;
+* ``inverse``: the post hoc inverse of the result (psi = phi^{-1} fitted by
+  the same loop on the inverse-consistency cost): time per fit and the final
+  cost;
 * ``use_jac``: the same registration with Algorithm 1's use_jac on (the
   Eulerian direction J(phi)^T dU/dphi), its time relative to the default
   Jacobian-free form, and its accuracy;
@@ -149,6 +152,35 @@ def run_use_jac(p, steps, params):
     field = pr.field()
     pr.close()
     return start.elapsed_time(end) / steps, float(loss[-1]), field
+
+
+def run_inverse(field, steps, params):
+    """The post hoc inverse of the registration's result (fa_inverse.h):
+    psi = phi^{-1} fitted over scales 4, 2, 1 at 100, 50, 25 iterations with
+    eta 0.2.  Returns milliseconds per fit (HIP events, after a warm-up fit),
+    the voxel-iterations of one fit and the cost history."""
+    import torch
+
+    from paper_2404_01249_amd import Inverse
+    scales, iters = [4.0, 2.0, 1.0], [100, 50, 25]
+    stream = torch.cuda.current_stream()
+    shp = tuple(int(n) for n in field.shape[1:])
+    vox = sum(int(np.prod([max(1, int(np.floor(n / s + 0.5))) for n in shp])) * it for s, it in zip(scales, iters))
+    inv = Inverse(field.contiguous(), eta=0.2, sigma_grad=params["sigma_grad"], sigma_warp=params["sigma_warp"],
+                  stream=stream)
+    inv.set_schedule(scales, iters)
+    inv.run()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        inv.set_schedule(scales, iters)
+        inv.run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    loss = inv.loss_history()
+    inv.close()
+    return start.elapsed_time(end) / steps, vox, loss
 
 
 def run_batch_compare(p, k, params):
@@ -328,6 +360,8 @@ def main():
                     help="variants per size in the grid-search batch (8 gives 96 registrations; 0 skips)")
     ap.add_argument("--grid-fused-only", action="store_true",
                     help="grid-search batch: skip the sequential comparison (for kernel traces)")
+    ap.add_argument("--inverse-steps", type=int, default=2,
+                    help="timed fits of the post hoc inverse of the result (0 skips)")
     ap.add_argument("--jac-steps", type=int, default=2,
                     help="registrations timed with use_jac on (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
@@ -425,6 +459,12 @@ def main():
                 "sequential_s": g["sequential"],
                 "sequential_voxel_iters_per_s": g["voxel_iters"] / g["sequential"],
                 "fused_speedup": g["sequential"] / g["fused"]})
+    if args.inverse_steps > 0:
+        ims, ivox, iloss = run_inverse(field, args.inverse_steps, params)
+        out["inverse"] = {"ms_per_fit": ims, "voxel_iters": ivox, "voxel_iters_per_s": ivox / (ims * 1e-3),
+                          "schedule": "scales [4.0, 2.0, 1.0] at [100, 50, 25], eta 0.2",
+                          "cost_first": float(iloss[0]), "cost_final": float(iloss[-1]),
+                          "rms_residual_final": float(np.sqrt(iloss[-1] / 2.0))}
     if args.jac_steps > 0:
         jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
         out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}

@@ -11,7 +11,7 @@ from . import evaluate, fa
 from .fa import FAError
 from .lncc import LNCC
 
-__all__ = ["Pair", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
+__all__ = ["Pair", "Inverse", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
 
 
 def run_batch(pairs, max_iters=1 << 30, fused=True):
@@ -115,6 +115,77 @@ class Pair:
     def close(self):
         if getattr(self, "handle", None):
             fa.fa_pair_destroy(self.handle)
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Inverse:
+    """The post hoc inverse psi = phi^{-1} of a warp phi = id + d
+    (fa_inverse.h): a (3, n0, n1, n2) float32 GPU tensor of displacements in
+    voxels.
+
+    >>> inv = Inverse(d, eta=0.1)
+    >>> inv.set_schedule([4, 2, 1], [100, 50, 25]); inv.run()
+    >>> e = inv.field()        # psi - id, (3, n0, n1, n2)
+    """
+
+    def __init__(self, d, *, eta=0.5, sigma_grad=1.0, sigma_warp=0.5, beta1=0.9, beta2=0.999,
+                 adam_eps=1e-8, stream=None):
+        import torch
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        p = fa.fa_params_default()
+        p.eta, p.sigma_grad, p.sigma_warp = eta, sigma_grad, sigma_warp
+        p.adam_beta1, p.adam_beta2, p.adam_eps = beta1, beta2, adam_eps
+        self.params = p
+        self.shape = tuple(int(s) for s in d.shape[1:])
+        self.handle = fa.fa_inverse_create(d, p, self.stream)
+        self._keep = d   # alive until the stream has copied it
+        self.total_iters = 0
+
+    def set_schedule(self, scales, iters):
+        fa.fa_inverse_set_schedule(self.handle, scales, iters)
+        self.total_iters = int(sum(iters))
+
+    def step(self, n):
+        return fa.fa_inverse_step(self.handle, n)
+
+    def run(self):
+        return fa.fa_inverse_step(self.handle, 1 << 30)[0]
+
+    def loss_history(self):
+        return fa.fa_inverse_get_loss(self.handle, self.total_iters)
+
+    def level_shape(self):
+        return fa.fa_inverse_get_field(self.handle, None)[1]
+
+    def field(self):
+        shp = self.level_shape()
+        out = self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda")
+        fa.fa_inverse_get_field(self.handle, out)
+        return out
+
+    def eval_gradient(self):
+        shp = self.level_shape()
+        g = self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda")
+        loss = fa.fa_inverse_eval_gradient(self.handle, g)
+        return g, loss
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fa.fa_inverse_destroy(self.handle)
             self.handle = None
             self._keep = None
 

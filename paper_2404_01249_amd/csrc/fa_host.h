@@ -37,6 +37,16 @@ enum KernelKind { KIND_GRAD = 0, KIND_SMOOTH_MAX = 1, KIND_WARP_SMOOTH = 2, KIND
 // kinds only).
 Tiling choose_tiling(const fa_shape& s, KernelKind kind, const Tuning& tu = Tuning(), bool cube_ok = false);
 
+// Sampled Gaussian taps exp(-k^2 / 2 sigma^2), |k| <= ceil(3 sigma), normalised
+// to sum 1 (in double); sigma <= 0 gives the single tap 1.  tap_radius: the
+// number of taps on each side.
+std::vector<float> gaussian_taps(float sigma);
+int tap_radius(float sigma);
+// Validates every field of fa_params (FA_EINVAL with a message).
+fa_status check_params(const fa_params* p);
+// Grid of a pyramid level: max(1, floor(n / scale + 1/2)) per axis.
+fa_shape level_shape(const fa_shape& s, float scale);
+
 // Chunk lengths of the march tilings ts (one per entry of a batched launch of
 // kernel `kind`, volumes of n0s[i] planes along n0, `halo` planes recomputed
 // per chunk) for the resident slots they share; entries with pinned[i] keep

@@ -23,9 +23,7 @@ using fa::Tiling;
 using fa::Tuning;
 using fa::voxels;
 
-namespace {
-
-thread_local std::string g_err;
+namespace fa {
 
 // Sampled Gaussian taps exp(-k^2 / 2 sigma^2), |k| <= ceil(3 sigma),
 // normalised to sum 1 (computed in double).  sigma <= 0 gives the single tap 1.
@@ -45,6 +43,40 @@ std::vector<float> gaussian_taps(float sigma_f) {
 }
 
 int tap_radius(float sigma) { return (int)(gaussian_taps(sigma).size() / 2); }
+
+fa_status check_params(const fa_params* p) {
+  if (!p) return fail(FA_EINVAL, "params is NULL");
+  if (!(p->eta > 0.0f) || !std::isfinite(p->eta)) return fail(FA_EINVAL, "eta must be a finite value > 0");
+  if (p->cc_window < 1 || p->cc_window > fa::kMaxWindow || (p->cc_window % 2) == 0)
+    return fail(FA_EINVAL, "cc_window must be odd and in [1, 9]");
+  if (!(p->cc_eps >= 0.0f) || !std::isfinite(p->cc_eps)) return fail(FA_EINVAL, "cc_eps must be finite and >= 0");
+  if (!(p->adam_beta1 >= 0.0f && p->adam_beta1 < 1.0f)) return fail(FA_EINVAL, "adam_beta1 must be in [0, 1)");
+  if (!(p->adam_beta2 >= 0.0f && p->adam_beta2 < 1.0f)) return fail(FA_EINVAL, "adam_beta2 must be in [0, 1)");
+  if (!(p->adam_eps >= 0.0f) || !std::isfinite(p->adam_eps)) return fail(FA_EINVAL, "adam_eps must be finite and >= 0");
+  if (!std::isfinite(p->sigma_grad) || !std::isfinite(p->sigma_warp))
+    return fail(FA_EINVAL, "sigma_grad and sigma_warp must be finite");
+  if (tap_radius(p->sigma_grad) > fa::kMaxRadius || tap_radius(p->sigma_warp) > fa::kMaxRadius)
+    return fail(FA_EINVAL, "Gaussian radius ceil(3 sigma) must be <= 6 (sigma <= 2 voxels)");
+  if (p->use_jac != 0 && p->use_jac != 1) return fail(FA_EINVAL, "use_jac must be 0 or 1");
+  return FA_OK;
+}
+
+fa_shape level_shape(const fa_shape& s, float scale) {
+  const double sc = (double)scale;
+  auto one = [&](int n) { return std::max(1, (int)std::floor((double)n / sc + 0.5)); };
+  return fa_shape{one(s.n0), one(s.n1), one(s.n2)};
+}
+
+}  // namespace fa
+
+using fa::check_params;
+using fa::gaussian_taps;
+using fa::level_shape;
+using fa::tap_radius;
+
+namespace {
+
+thread_local std::string g_err;
 
 struct Level {
   fa_shape shape{};
@@ -141,29 +173,8 @@ fa_status dalloc(T** out, size_t count, const char* what) {
   return FA_OK;
 }
 
-fa_status check_params(const fa_params* p) {
-  if (!p) return fail(FA_EINVAL, "params is NULL");
-  if (!(p->eta > 0.0f) || !std::isfinite(p->eta)) return fail(FA_EINVAL, "eta must be a finite value > 0");
-  if (p->cc_window < 1 || p->cc_window > fa::kMaxWindow || (p->cc_window % 2) == 0)
-    return fail(FA_EINVAL, "cc_window must be odd and in [1, 9]");
-  if (!(p->cc_eps >= 0.0f) || !std::isfinite(p->cc_eps)) return fail(FA_EINVAL, "cc_eps must be finite and >= 0");
-  if (!(p->adam_beta1 >= 0.0f && p->adam_beta1 < 1.0f)) return fail(FA_EINVAL, "adam_beta1 must be in [0, 1)");
-  if (!(p->adam_beta2 >= 0.0f && p->adam_beta2 < 1.0f)) return fail(FA_EINVAL, "adam_beta2 must be in [0, 1)");
-  if (!(p->adam_eps >= 0.0f) || !std::isfinite(p->adam_eps)) return fail(FA_EINVAL, "adam_eps must be finite and >= 0");
-  if (!std::isfinite(p->sigma_grad) || !std::isfinite(p->sigma_warp))
-    return fail(FA_EINVAL, "sigma_grad and sigma_warp must be finite");
-  if (tap_radius(p->sigma_grad) > fa::kMaxRadius || tap_radius(p->sigma_warp) > fa::kMaxRadius)
-    return fail(FA_EINVAL, "Gaussian radius ceil(3 sigma) must be <= 6 (sigma <= 2 voxels)");
-  if (p->use_jac != 0 && p->use_jac != 1) return fail(FA_EINVAL, "use_jac must be 0 or 1");
-  return FA_OK;
-}
 
 
-fa_shape level_shape(const fa_shape& s, float scale) {
-  const double sc = (double)scale;
-  auto one = [&](int n) { return std::max(1, (int)std::floor((double)n / sc + 0.5)); };
-  return fa_shape{one(s.n0), one(s.n1), one(s.n2)};
-}
 
 // Blur (sigma = scale/2, replicate) then resample at corner-aligned positions.
 fa_status build_level_image(fa_pair P, const float* src, float* dst, const Level& L, int off) {

@@ -70,6 +70,13 @@ SIGNATURES = {
     "fa_batch_step": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
     "fa_batch_step_fused": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
     "fa_plan_tiling": (_I, [_I, _I, ctypes.POINTER(fa_shape), _I, _I, _IP, _IP]),
+    "fa_inverse_create": (_I, [_P, fa_shape, ctypes.POINTER(fa_params), _P, ctypes.POINTER(_P)]),
+    "fa_inverse_set_schedule": (_I, [_P, _I, _FP, _IP]),
+    "fa_inverse_step": (_I, [_P, _I, _IP, _IP]),
+    "fa_inverse_get_field": (_I, [_P, _P, _IP, ctypes.POINTER(fa_shape)]),
+    "fa_inverse_get_loss": (_I, [_P, _FP, _I, _IP]),
+    "fa_inverse_eval_gradient": (_I, [_P, _P, _FP]),
+    "fa_inverse_destroy": (None, [_P]),
     "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
     "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "fa_lncc_destroy": (None, [_P]),
@@ -312,6 +319,55 @@ def fa_plan_tiling(kind: int, shapes, halo: int, batched: bool):
     nb = (ctypes.c_int * n)()
     _check(load_library().fa_plan_tiling(int(kind), n, arr, int(halo), int(bool(batched)), zc, nb))
     return list(zc), list(nb)
+
+
+def fa_inverse_create(d, params: fa_params, stream=None) -> int:
+    if d.dim() != 4 or d.shape[0] != 3:
+        raise ValueError("d must be a (3, n0, n1, n2) displacement")
+    shape = fa_shape(*[int(s) for s in d.shape[1:]])
+    h = _P()
+    _check(load_library().fa_inverse_create(_ptr(d), shape, ctypes.byref(params), _stream_handle(stream),
+                                            ctypes.byref(h)))
+    return h.value
+
+
+def fa_inverse_set_schedule(h: int, scales, iters):
+    scales = np.ascontiguousarray(scales, dtype=np.float32)
+    iters = np.ascontiguousarray(iters, dtype=np.int32)
+    if scales.shape != iters.shape or scales.ndim != 1:
+        raise ValueError("scales and iters must be 1-D of equal length")
+    _check(load_library().fa_inverse_set_schedule(h, len(scales), scales.ctypes.data_as(_FP),
+                                                  iters.ctypes.data_as(_IP)))
+
+
+def fa_inverse_step(h: int, max_iters: int) -> tuple[int, int]:
+    done, fin = ctypes.c_int(0), ctypes.c_int(0)
+    _check(load_library().fa_inverse_step(h, int(max_iters), ctypes.byref(done), ctypes.byref(fin)))
+    return done.value, fin.value
+
+
+def fa_inverse_get_field(h: int, dev_out=None) -> tuple[int, tuple]:
+    lvl, shp = ctypes.c_int(0), fa_shape()
+    _check(load_library().fa_inverse_get_field(h, _ptr(dev_out), ctypes.byref(lvl), ctypes.byref(shp)))
+    return lvl.value, (shp.n0, shp.n1, shp.n2)
+
+
+def fa_inverse_get_loss(h: int, capacity: int) -> np.ndarray:
+    out = np.zeros(max(int(capacity), 0), dtype=np.float32)
+    n = ctypes.c_int(0)
+    _check(load_library().fa_inverse_get_loss(h, out.ctypes.data_as(_FP), len(out), ctypes.byref(n)))
+    return out[: n.value]
+
+
+def fa_inverse_eval_gradient(h: int, g_dev) -> float:
+    loss = ctypes.c_float(0.0)
+    _check(load_library().fa_inverse_eval_gradient(h, _ptr(g_dev), ctypes.byref(loss)))
+    return loss.value
+
+
+def fa_inverse_destroy(h: int):
+    if h:
+        load_library().fa_inverse_destroy(h)
 
 
 def fa_batch_step_fused(pairs, max_iters: int) -> int:

@@ -134,3 +134,22 @@ def test_plan_tiling_rejects_bad_arguments(lib):
     assert lib.fa_plan_tiling(0, 1, arr, -1, 0, None, None) == fa.FA_EINVAL
     bad = (fa.fa_shape * 1)(fa.fa_shape(1, 10, 10))
     assert lib.fa_plan_tiling(0, 1, bad, 0, 0, None, None) == fa.FA_ESHAPE
+
+
+def test_inverse_rejects_bad_arguments_before_any_device_work(lib):
+    p = fa.fa_params_default()
+    shp = fa.fa_shape(8, 9, 10)
+    h = ctypes.c_void_p(0)
+    assert lib.fa_inverse_create(None, shp, ctypes.byref(p), None, ctypes.byref(h)) == fa.FA_EINVAL
+    assert lib.fa_inverse_create(ctypes.c_void_p(16), shp, ctypes.byref(p), None, None) == fa.FA_EINVAL
+    assert lib.fa_inverse_create(ctypes.c_void_p(16), fa.fa_shape(1, 9, 10), ctypes.byref(p), None,
+                                 ctypes.byref(h)) == fa.FA_ESHAPE
+    bad = fa.fa_params_default()
+    bad.eta = -1.0
+    assert lib.fa_inverse_create(ctypes.c_void_p(16), shp, ctypes.byref(bad), None, ctypes.byref(h)) == fa.FA_EINVAL
+    assert lib.fa_inverse_set_schedule(None, 1, None, None) == fa.FA_EINVAL
+    assert lib.fa_inverse_step(None, 1, None, None) == fa.FA_EINVAL
+    assert lib.fa_inverse_get_field(None, None, None, None) == fa.FA_EINVAL
+    assert lib.fa_inverse_get_loss(None, None, 0, None) == fa.FA_EINVAL
+    assert lib.fa_inverse_eval_gradient(None, None, None) == fa.FA_EINVAL
+    lib.fa_inverse_destroy(None)
