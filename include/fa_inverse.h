@@ -75,6 +75,12 @@ fa_status fa_inverse_get_loss(fa_inverse h, float* host_out, int capacity, int* 
  * given).  Changes no state.  FA_EINVAL, FA_ESTATE, FA_EHIP. */
 fa_status fa_inverse_eval_gradient(fa_inverse h, float* g_dev, float* loss_host);
 
+/* Splat form (a tuning and test switch): 0 (default) sums each brick's
+ * contributions in LDS and adds each touched node once; 1 adds every
+ * contribution with its own global atomic.  Both add the same fixed-point
+ * integers, so results are bitwise equal.  FA_EINVAL. */
+fa_status fa_inverse_set_splat(fa_inverse h, int direct);
+
 /* Releases the handle (synchronises with its stream first).  NULL is a
  * no-op. */
 void fa_inverse_destroy(fa_inverse h);

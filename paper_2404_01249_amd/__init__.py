@@ -183,6 +183,9 @@ class Inverse:
         loss = fa.fa_inverse_eval_gradient(self.handle, g)
         return g, loss
 
+    def set_splat(self, direct):
+        fa.fa_inverse_set_splat(self.handle, direct)
+
     def close(self):
         if getattr(self, "handle", None):
             fa.fa_inverse_destroy(self.handle)

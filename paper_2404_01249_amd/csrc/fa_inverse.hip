@@ -138,6 +138,138 @@ k_inv_splat(const float* __restrict__ d, const float* __restrict__ e, unsigned l
   if (threadIdx.x == 0) part[blockIdx.x] = -s;
 }
 
+// The same splat by bricks of 4 x 8 x 16 voxels (two per thread).  A smooth
+// warp sends a brick's samples into a box of nodes little larger than the
+// brick: the workgroup sums its contributions there with LDS atomics (the
+// same fixed-point integers, so the result is bitwise that of the direct
+// form), then adds each non-zero box node to acc with one global atomic per
+// component.  A brick whose box exceeds kBoxNodes (a folded or wildly varying
+// warp) scatters directly.
+constexpr int kBZ = 4, kBY = 8, kBX = 16;
+constexpr int kBoxNodes = 2048;   // 3 x 2048 x 8 B = 48 KiB of LDS
+
+__global__ void __launch_bounds__(kInvThreads)
+k_inv_splat_lds(const float* __restrict__ d, const float* __restrict__ e, unsigned long long* __restrict__ acc,
+                double* __restrict__ part, int n0, int n1, int n2) {
+  __shared__ unsigned long long box[3 * kBoxNodes];
+  __shared__ int bb[6];   // box: lo0, lo1, lo2, hi0, hi1, hi2 (inclusive)
+  __shared__ double red[kInvThreads / 64];
+  constexpr int VPT = kBZ * kBY * kBX / kInvThreads;
+  const int N = n0 * n1 * n2;
+  const int tz = (n0 + kBZ - 1) / kBZ, ty = (n1 + kBY - 1) / kBY, tx = (n2 + kBX - 1) / kBX;
+  const int nbricks = tz * ty * tx;
+  const int tid = threadIdx.x;
+  double loss = 0.0;
+  for (int b = blockIdx.x; b < nbricks; b += gridDim.x) {
+    const int bx = b % tx, by = (b / tx) % ty, bz = b / (tx * ty);
+    int cz[VPT], cy[VPT], cx[VPT];
+    float t0[VPT], t1[VPT], t2[VPT], r[VPT][3];
+    bool valid[VPT];
+    int lo0 = 1 << 30, lo1 = 1 << 30, lo2 = 1 << 30, hi0 = -(1 << 30), hi1 = -(1 << 30), hi2 = -(1 << 30);
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int l = tid + k * kInvThreads;
+      const int z = bz * kBZ + l / (kBY * kBX), y = by * kBY + (l / kBX) % kBY, x = bx * kBX + l % kBX;
+      valid[k] = z < n0 && y < n1 && x < n2;
+      cz[k] = cy[k] = cx[k] = 0;
+      t0[k] = t1[k] = t2[k] = 0.0f;
+      r[k][0] = r[k][1] = r[k][2] = 0.0f;
+      if (valid[k]) {
+        const int i = (z * n1 + y) * n2 + x;
+        const float d0 = d[i], d1 = d[N + i], d2 = d[2 * N + i];
+        const Cell c = cell_of((float)z + d0, (float)y + d1, (float)x + d2, n0, n1, n2);
+        r[k][0] = d0 + sample(e, c);
+        r[k][1] = d1 + sample(e + N, c);
+        r[k][2] = d2 + sample(e + 2 * N, c);
+        loss += (double)(r[k][0] * r[k][0] + r[k][1] * r[k][1] + r[k][2] * r[k][2]);
+        t0[k] = c.t0;
+        t1[k] = c.t1;
+        t2[k] = c.t2;
+        // the cell's lower corner (clamped as in cell_of: off-grid corners are dropped below)
+        cz[k] = (int)fminf(fmaxf(floorf((float)z + d0), -2.0f), (float)n0);
+        cy[k] = (int)fminf(fmaxf(floorf((float)y + d1), -2.0f), (float)n1);
+        cx[k] = (int)fminf(fmaxf(floorf((float)x + d2), -2.0f), (float)n2);
+        lo0 = min(lo0, cz[k]);
+        lo1 = min(lo1, cy[k]);
+        lo2 = min(lo2, cx[k]);
+        hi0 = max(hi0, cz[k] + 1);
+        hi1 = max(hi1, cy[k] + 1);
+        hi2 = max(hi2, cx[k] + 1);
+      }
+    }
+    if (tid == 0) {
+      bb[0] = bb[1] = bb[2] = 1 << 30;
+      bb[3] = bb[4] = bb[5] = -(1 << 30);
+    }
+    __syncthreads();
+    atomicMin(&bb[0], lo0);
+    atomicMin(&bb[1], lo1);
+    atomicMin(&bb[2], lo2);
+    atomicMax(&bb[3], hi0);
+    atomicMax(&bb[4], hi1);
+    atomicMax(&bb[5], hi2);
+    __syncthreads();
+    // the box clipped to the grid (nodes off the grid receive nothing)
+    const int b0 = max(bb[0], 0), b1 = max(bb[1], 0), b2 = max(bb[2], 0);
+    const int e0 = min(bb[3], n0 - 1), e1 = min(bb[4], n1 - 1), e2 = min(bb[5], n2 - 1);
+    const int s0 = e0 - b0 + 1, s1 = e1 - b1 + 1, s2 = e2 - b2 + 1;
+    const bool empty = s0 <= 0 || s1 <= 0 || s2 <= 0;
+    const int nb = empty ? 0 : s0 * s1 * s2;
+    if (nb <= kBoxNodes) {
+      for (int q = tid; q < 3 * nb; q += kInvThreads) box[q] = 0ull;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < VPT; ++k) {
+        if (!valid[k]) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int o0 = (j >> 2) & 1, o1 = (j >> 1) & 1, o2 = j & 1;
+          const int z = cz[k] + o0, y = cy[k] + o1, x = cx[k] + o2;
+          if (z < 0 || z >= n0 || y < 0 || y >= n1 || x < 0 || x >= n2) continue;
+          const float w = (o0 ? t0[k] : 1.0f - t0[k]) * (o1 ? t1[k] : 1.0f - t1[k]) * (o2 ? t2[k] : 1.0f - t2[k]);
+          if (w == 0.0f) continue;
+          const int q = ((z - b0) * s1 + (y - b1)) * s2 + (x - b2);
+          const float w2 = 2.0f * w;
+          atomicAdd(&box[q], to_fixed(w2 * r[k][0]));
+          atomicAdd(&box[nb + q], to_fixed(w2 * r[k][1]));
+          atomicAdd(&box[2 * nb + q], to_fixed(w2 * r[k][2]));
+        }
+      }
+      __syncthreads();
+      for (int q = tid; q < nb; q += kInvThreads) {
+        const int x = b2 + q % s2, y = b1 + (q / s2) % s1, z = b0 + q / (s1 * s2);
+        const int gi = (z * n1 + y) * n2 + x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const unsigned long long v = box[c * nb + q];
+          if (v != 0ull) atomicAdd(&acc[c * N + gi], v);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < VPT; ++k) {
+        if (!valid[k]) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int o0 = (j >> 2) & 1, o1 = (j >> 1) & 1, o2 = j & 1;
+          const int z = cz[k] + o0, y = cy[k] + o1, x = cx[k] + o2;
+          if (z < 0 || z >= n0 || y < 0 || y >= n1 || x < 0 || x >= n2) continue;
+          const float w = (o0 ? t0[k] : 1.0f - t0[k]) * (o1 ? t1[k] : 1.0f - t1[k]) * (o2 ? t2[k] : 1.0f - t2[k]);
+          if (w == 0.0f) continue;
+          const int gi = (z * n1 + y) * n2 + x;
+          const float w2 = 2.0f * w;
+          atomicAdd(&acc[gi], to_fixed(w2 * r[k][0]));
+          atomicAdd(&acc[N + gi], to_fixed(w2 * r[k][1]));
+          atomicAdd(&acc[2 * N + gi], to_fixed(w2 * r[k][2]));
+        }
+      }
+    }
+    __syncthreads();   // box and bb are reused by the next brick
+  }
+  const double s = block_sum256(loss, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = -s;
+}
+
 // r2(x) = e(x) + d(x + e(x)), the residual of phi o psi, whose derivative in
 // e(x) is 2 (I + grad d)^T r2; with the splat's sum (acc, cleared here for the
 // next iteration) and the 1/N of the mean this is dU/de.  grad_only: write it
@@ -243,6 +375,7 @@ struct fa_inverse_s {
   int rg = 0, rw = 0, off_g = 0, off_w = 0, off_one = 0;
   int cur_level = 0, cur_iter = 0, t_done = 0, iters_done = 0;
   bool scheduled = false;
+  bool splat_direct = false;   // the per-voxel global-atomic splat instead of the brick form
 };
 
 namespace {
@@ -296,8 +429,13 @@ bool schedule_done(const fa_inverse H) {
 fa_status launch_direction(fa_inverse H, const ILevel& L, float* out, int grad_only) {
   const fa_shape& s = L.shape;
   const int b = inv_blocks(L.n);
-  hipLaunchKernelGGL(k_inv_splat, dim3(b), dim3(kInvThreads), 0, H->stream, L.d, H->e, H->acc, H->partials,
-                     s.n0, s.n1, s.n2);
+  if (H->splat_direct) {
+    hipLaunchKernelGGL(k_inv_splat, dim3(b), dim3(kInvThreads), 0, H->stream, L.d, H->e, H->acc, H->partials,
+                       s.n0, s.n1, s.n2);
+  } else {
+    hipLaunchKernelGGL(k_inv_splat_lds, dim3(b), dim3(kInvThreads), 0, H->stream, L.d, H->e, H->acc,
+                       H->partials, s.n0, s.n1, s.n2);
+  }
   FA_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_inv_dir, dim3(b), dim3(kInvThreads), 0, H->stream, L.d, H->e, H->acc, H->m, H->v, out,
                      H->ctl, H->partials + b, s.n0, s.n1, s.n2, (float)(1.0 / (double)L.n), H->p.adam_beta1,
@@ -564,6 +702,13 @@ fa_status fa_inverse_eval_gradient(fa_inverse H, float* g_dev, float* loss_host)
     FA_HIP(hipMemcpyAsync(loss_host, H->scalar, sizeof(float), hipMemcpyDeviceToHost, H->stream));
     FA_HIP(hipStreamSynchronize(H->stream));
   }
+  return FA_OK;
+}
+
+fa_status fa_inverse_set_splat(fa_inverse H, int direct) {
+  if (!H) return fail(FA_EINVAL, "handle is NULL");
+  if (direct != 0 && direct != 1) return fail(FA_EINVAL, "direct must be 0 or 1");
+  H->splat_direct = direct != 0;
   return FA_OK;
 }
 

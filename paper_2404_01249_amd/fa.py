@@ -77,6 +77,7 @@ SIGNATURES = {
     "fa_inverse_get_loss": (_I, [_P, _FP, _I, _IP]),
     "fa_inverse_eval_gradient": (_I, [_P, _P, _FP]),
     "fa_inverse_destroy": (None, [_P]),
+    "fa_inverse_set_splat": (_I, [_P, _I]),
     "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
     "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "fa_lncc_destroy": (None, [_P]),
@@ -363,6 +364,10 @@ def fa_inverse_eval_gradient(h: int, g_dev) -> float:
     loss = ctypes.c_float(0.0)
     _check(load_library().fa_inverse_eval_gradient(h, _ptr(g_dev), ctypes.byref(loss)))
     return loss.value
+
+
+def fa_inverse_set_splat(h: int, direct: bool):
+    _check(load_library().fa_inverse_set_splat(h, int(bool(direct))))
 
 
 def fa_inverse_destroy(h: int):

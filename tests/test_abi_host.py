@@ -152,4 +152,5 @@ def test_inverse_rejects_bad_arguments_before_any_device_work(lib):
     assert lib.fa_inverse_get_field(None, None, None, None) == fa.FA_EINVAL
     assert lib.fa_inverse_get_loss(None, None, 0, None) == fa.FA_EINVAL
     assert lib.fa_inverse_eval_gradient(None, None, None) == fa.FA_EINVAL
+    assert lib.fa_inverse_set_splat(None, 0) == fa.FA_EINVAL
     lib.fa_inverse_destroy(None)

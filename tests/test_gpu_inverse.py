@@ -124,6 +124,34 @@ def test_runs_are_bitwise_reproducible():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("wild", [False, True], ids=["smooth", "wild"])
+def test_brick_splat_is_bitwise_the_direct_splat(wild):
+    """The LDS brick splat adds the same fixed-point integers as the direct
+    one.  A wild (unsmoothed, large) field sends bricks' samples far apart, so
+    their boxes overflow LDS and take the direct path inside the brick kernel."""
+    shape = (19, 23, 37)
+    if wild:
+        d = np.random.default_rng(106).uniform(-6.0, 6.0, (3,) + shape).astype(np.float32)
+    else:
+        d = warp_field(shape, 106, 3.0)
+    out = []
+    for direct in (True, False):
+        with Inverse(dev(d), eta=0.5) as inv:
+            inv.set_splat(direct)
+            inv.set_schedule([2.0, 1.0], [3, 3])
+            g0, _ = inv.eval_gradient()
+            g0 = host(g0)
+            inv.run()
+            out.append((g0, host(inv.field()), inv.loss_history()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+    if wild:
+        d64 = d.astype(np.float64)
+        ds = V.downsample_field(d64, 2.0)
+        ref, _ = V.inverse_gradient(ds, np.zeros_like(ds))
+        assert rel_l2(out[1][0], ref) <= TOL_G
+
+
 def test_zero_warp_keeps_the_identity():
     with Inverse(torch.zeros((3, 8, 9, 10), device="cuda")) as inv:
         inv.set_schedule([1.0], [3])
