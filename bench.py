@@ -25,6 +25,9 @@ Prints one JSON line.  Besides the headline value it reports
 * ``inverse``: the post hoc inverse of the result (psi = phi^{-1} fitted by
   the same loop on the inverse-consistency cost): time per fit and the final
   cost;
+* ``symmetric``: the symmetric registration (two half-way warps, then
+  phi = phi_M o phi_F^{-1}): time per registration relative to the
+  asymmetric one, and its accuracy;
 * ``use_jac``: the same registration with Algorithm 1's use_jac on (the
   Eulerian direction J(phi)^T dU/dphi), its time relative to the default
   Jacobian-free form, and its accuracy;
@@ -181,6 +184,39 @@ def run_inverse(field, steps, params):
     loss = inv.loss_history()
     inv.close()
     return start.elapsed_time(end) / steps, vox, loss
+
+
+def run_symmetric(p, steps, params):
+    """Symmetric registration of the workload (fa_symmetric.h): the two
+    half-way warps over the workload's schedule, then phi_F inverted over
+    scales 4, 2, 1 at 100, 50, 25 (eta 0.2) and composed with phi_M.
+    Returns milliseconds per registration (HIP events, after a warm-up), the
+    half-way cost history and the final field."""
+    import torch
+
+    from paper_2404_01249_amd import Symmetric
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    stream = torch.cuda.current_stream()
+    sy = Symmetric(fixed, moving, stream=stream, **params)
+
+    def once():
+        sy.set_schedule(p.scales, p.iters)
+        sy.run()
+        return sy.finish([4.0, 2.0, 1.0], [100, 50, 25], eta=0.2, sigma_grad=params["sigma_grad"],
+                         sigma_warp=params["sigma_warp"])
+
+    once()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        d = once()
+    end.record(stream)
+    torch.cuda.synchronize()
+    loss = sy.loss_history()
+    sy.close()
+    return start.elapsed_time(end) / steps, loss, d
 
 
 def run_batch_compare(p, k, params):
@@ -362,6 +398,8 @@ def main():
                     help="grid-search batch: skip the sequential comparison (for kernel traces)")
     ap.add_argument("--inverse-steps", type=int, default=2,
                     help="timed fits of the post hoc inverse of the result (0 skips)")
+    ap.add_argument("--sym-steps", type=int, default=2,
+                    help="timed symmetric registrations (0 skips)")
     ap.add_argument("--jac-steps", type=int, default=2,
                     help="registrations timed with use_jac on (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
@@ -465,6 +503,11 @@ def main():
                           "schedule": "scales [4.0, 2.0, 1.0] at [100, 50, 25], eta 0.2",
                           "cost_first": float(iloss[0]), "cost_final": float(iloss[-1]),
                           "rms_residual_final": float(np.sqrt(iloss[-1] / 2.0))}
+    if args.sym_steps > 0:
+        sms, sloss, sfield = run_symmetric(p, args.sym_steps, params)
+        out["symmetric"] = {"ms_per_step": sms, "runtime_ratio": sms / ms, "final_halfway_loss": float(sloss[-1]),
+                            "inverse": "scales [4.0, 2.0, 1.0] at [100, 50, 25], eta 0.2",
+                            "accuracy": accuracy(p, sfield)}
     if args.jac_steps > 0:
         jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
         out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}

@@ -11,7 +11,7 @@ from . import evaluate, fa
 from .fa import FAError
 from .lncc import LNCC
 
-__all__ = ["Pair", "Inverse", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
+__all__ = ["Pair", "Inverse", "Symmetric", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
 
 
 def run_batch(pairs, max_iters=1 << 30, fused=True):
@@ -189,6 +189,82 @@ class Inverse:
     def close(self):
         if getattr(self, "handle", None):
             fa.fa_inverse_destroy(self.handle)
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Symmetric:
+    """Symmetric registration (fa_symmetric.h): two half-way warps meet in the
+    middle, then phi = phi_M o phi_F^{-1}.
+
+    >>> s = Symmetric(fixed, moving, eta=0.5, window=5)
+    >>> s.set_schedule([4, 2, 1], [200, 100, 50]); s.run()
+    >>> d = s.finish([4, 2, 1], [100, 50, 25], eta=0.2)   # (3, n0, n1, n2)
+    """
+
+    def __init__(self, fixed, moving, *, eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5,
+                 cc_eps=1e-5, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_jac=False, stream=None):
+        import torch
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        p = fa.fa_params_default()
+        p.eta, p.sigma_grad, p.sigma_warp, p.cc_window = eta, sigma_grad, sigma_warp, window
+        p.cc_eps, p.adam_beta1, p.adam_beta2, p.adam_eps = cc_eps, beta1, beta2, adam_eps
+        p.use_jac = 1 if use_jac else 0
+        self.params = p
+        self.shape = tuple(int(s) for s in fixed.shape)
+        self.handle = fa.fa_sym_create(fixed, moving, p, self.stream)
+        self._keep = (fixed, moving)
+        self.total_iters = 0
+
+    def set_schedule(self, scales, iters):
+        fa.fa_sym_set_schedule(self.handle, scales, iters)
+        self.total_iters = int(sum(iters))
+
+    def step(self, n):
+        return fa.fa_sym_step(self.handle, n)
+
+    def run(self):
+        return fa.fa_sym_step(self.handle, 1 << 30)[0]
+
+    def loss_history(self):
+        return fa.fa_sym_get_loss(self.handle, self.total_iters)
+
+    def halfway(self):
+        """(d_F, d_M) at the current level."""
+        shp = fa.fa_sym_get_halfway(self.handle)[1]
+        dF = self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda")
+        dM = self._torch.empty((3,) + shp, dtype=self._torch.float32, device="cuda")
+        fa.fa_sym_get_halfway(self.handle, dF, dM)
+        return dF, dM
+
+    def finish(self, scales, iters, *, eta=0.2, sigma_grad=1.0, sigma_warp=0.5, beta1=0.9, beta2=0.999,
+               adam_eps=1e-8):
+        """phi = phi_M o phi_F^{-1} (phi_F inverted over the given schedule):
+        returns its displacement and stores the inverse fit's last cost in
+        ``self.inverse_cost``."""
+        p = fa.fa_params_default()
+        p.eta, p.sigma_grad, p.sigma_warp = eta, sigma_grad, sigma_warp
+        p.adam_beta1, p.adam_beta2, p.adam_eps = beta1, beta2, adam_eps
+        d = self._torch.empty((3,) + self.shape, dtype=self._torch.float32, device="cuda")
+        self.inverse_cost = fa.fa_sym_finish(self.handle, p, scales, iters, d)
+        return d
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fa.fa_sym_destroy(self.handle)
             self.handle = None
             self._keep = None
 

@@ -128,6 +128,9 @@ hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int 
 hipError_t launch_warp(const float* img, const float* d, float* out, int n0, int n1, int n2,
                        hipStream_t s);
 hipError_t launch_soa_to_aos(const float* in, float* out, int64_t n, hipStream_t s);
+// out = u + d(x + u) ([3][n] fields; out must not alias d).
+hipError_t launch_compose_fields(const float* u, const float* d, float* out, int n0, int n1, int n2,
+                                 hipStream_t s);
 // Sets the Adam step count to t_done + 1 (bias corrections in double), clears
 // M and the completion counter; iter >= 0 also resets the iteration counter.
 hipError_t launch_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int iter, hipStream_t s);

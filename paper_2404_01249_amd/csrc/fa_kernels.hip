@@ -1794,6 +1794,25 @@ __global__ void k_warp(const float* __restrict__ img, const float* __restrict__ 
   out[i] = gather_value(g);
 }
 
+// out = u + d(x + u): the displacement of phi o (id + u) for phi = id + d,
+// with d sampled trilinearly per component (zero outside the grid).
+__global__ void k_compose_fields(const float* __restrict__ u, const float* __restrict__ d,
+                                 float* __restrict__ out, int n0, int n1, int n2) {
+  const int N = n0 * n1 * n2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int x = i % n2, y = (i / n2) % n1, z = i / (n1 * n2);
+  const float u0 = u[i], u1 = u[N + i], u2 = u[2 * N + i];
+  const Cell8 c = cell8_at(n0, n1, n2, z, y, x, u0, u1, u2);
+  Gather g0, g1, g2;
+  gather_issue(d, c, g0);
+  gather_issue(d + N, c, g1);
+  gather_issue(d + 2 * N, c, g2);
+  out[i] = u0 + gather_value(g0);
+  out[N + i] = u1 + gather_value(g1);
+  out[2 * N + i] = u2 + gather_value(g2);
+}
+
 __global__ void k_soa_to_aos(const float* __restrict__ in, float* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -2208,6 +2227,13 @@ hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int 
 hipError_t launch_warp(const float* img, const float* d, float* out, int n0, int n1, int n2, hipStream_t s) {
   const int64_t n = (int64_t)n0 * n1 * n2;
   hipLaunchKernelGGL(k_warp, dim3(grid1(n, 256)), dim3(256), 0, s, img, d, out, n0, n1, n2);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_fields(const float* u, const float* d, float* out, int n0, int n1, int n2,
+                                hipStream_t s) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  hipLaunchKernelGGL(k_compose_fields, dim3(grid1(n, 256)), dim3(256), 0, s, u, d, out, n0, n1, n2);
   return hipGetLastError();
 }
 

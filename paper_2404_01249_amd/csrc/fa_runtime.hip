@@ -13,6 +13,8 @@
 #include "fa_batch.h"
 #include "fa_host.h"
 #include "fa_inspect.h"
+#include "fa_inverse.h"
+#include "fa_symmetric.h"
 #include "fa_internal.h"
 
 using fa::check_shape;
@@ -232,10 +234,13 @@ struct IterPlan {
   int epi[3];
 };
 
-void plan_iteration(fa_pair P, const Level& L, IterPlan& it) {
+// fixed: the image the pair is registered to this iteration (NULL: the
+// level's own fixed image; the symmetric registration passes the other
+// half's warped image).
+void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed = nullptr) {
   fa::GradArgs& ga = it.ga;
   ga = fa::GradArgs{};
-  ga.fixed = L.fixed;
+  ga.fixed = fixed ? fixed : L.fixed;
   ga.moving_pad = L.moving_pad;
   ga.d = P->d;
   ga.m = P->m;
@@ -320,7 +325,7 @@ fa_status launch_eulerian(fa_pair P, const Level& L) {
   return FA_OK;
 }
 
-fa_status launch_iteration(fa_pair P, const Level& L) {
+fa_status launch_iteration(fa_pair P, const Level& L, const float* fixed = nullptr) {
   fa_pair_s::Pending pe{};
   pe.level = P->cur_level;
   if (P->profiling) {
@@ -328,7 +333,7 @@ fa_status launch_iteration(fa_pair P, const Level& L) {
     FA_HIP(hipEventRecord(pe.e[0], P->stream));
   }
   IterPlan it;
-  plan_iteration(P, L, it);
+  plan_iteration(P, L, it, fixed);
   FA_HIP(fa::launch_grad(it.ga, it.window, it.tg, P->stream));
   if (P->p.use_jac) FA_TRY(launch_eulerian(P, L));
   if (P->profiling) FA_HIP(hipEventRecord(pe.e[1], P->stream));
@@ -1207,6 +1212,159 @@ fa_status fa_pair_get_profile(fa_pair P, int level, int kind, double* total_ms, 
   if (total_ms) *total_ms = slot < P->prof_ms.size() ? P->prof_ms[slot] : 0.0;
   if (launches) *launches = slot < P->prof_n.size() ? P->prof_n[slot] : 0;
   return FA_OK;
+}
+
+}  // extern "C"
+
+// ---- fa_symmetric.h ---------------------------------------------------------
+// Two pairs share the handle's stream: M registers I_M (its moving image)
+// toward I_F o phi_F, F registers I_F toward I_M o phi_M.  Each pair's
+// level-l fixed image is the other side's level-l image; the warped images
+// replace it as the fixed image of every iteration.
+struct fa_sym_s {
+  fa_pair F = nullptr;
+  fa_pair M = nullptr;
+  float* wf = nullptr;   // I_F o phi_F at the current level
+  float* wm = nullptr;   // I_M o phi_M
+  int64_t wcap = 0;
+  hipStream_t stream = nullptr;
+  fa_shape shape{};
+};
+
+extern "C" {
+
+fa_status fa_sym_create(const float* fixed, const float* moving, fa_shape shape, const fa_params* params,
+                        void* stream, fa_sym* out) {
+  if (!out) return fail(FA_EINVAL, "out is NULL");
+  *out = nullptr;
+  fa_sym H = new (std::nothrow) fa_sym_s();
+  if (!H) return fail(FA_ENOMEM, "host allocation failed");
+  H->stream = (hipStream_t)stream;
+  H->shape = shape;
+  fa_status st = fa_pair_create(moving, fixed, shape, params, stream, &H->F);
+  if (st == FA_OK) st = fa_pair_create(fixed, moving, shape, params, stream, &H->M);
+  if (st != FA_OK) {
+    fa_pair_destroy(H->F);
+    delete H;
+    return st;
+  }
+  *out = H;
+  return FA_OK;
+}
+
+fa_status fa_sym_set_schedule(fa_sym H, int n_levels, const float* scales, const int* iters) {
+  if (!H) return fail(FA_EINVAL, "handle is NULL");
+  FA_TRY(fa_pair_set_schedule(H->F, n_levels, scales, iters));
+  FA_TRY(fa_pair_set_schedule(H->M, n_levels, scales, iters));
+  int64_t nmax = 0;
+  for (const Level& L : H->M->levels) nmax = std::max(nmax, L.n);
+  if (nmax > H->wcap) {
+    FA_HIP(hipStreamSynchronize(H->stream));
+    if (H->wf) (void)hipFree(H->wf);
+    if (H->wm) (void)hipFree(H->wm);
+    H->wf = H->wm = nullptr;
+    H->wcap = 0;
+    FA_TRY(dalloc(&H->wf, (size_t)nmax, "warped image"));
+    FA_TRY(dalloc(&H->wm, (size_t)nmax, "warped image"));
+    H->wcap = nmax;
+  }
+  return FA_OK;
+}
+
+fa_status fa_sym_step(fa_sym H, int max_iters, int* iters_done, int* finished) {
+  if (iters_done) *iters_done = 0;
+  if (finished) *finished = 0;
+  if (!H) return fail(FA_EINVAL, "handle is NULL");
+  if (!H->F->scheduled || !H->M->scheduled) return fail(FA_ESTATE, "fa_sym_set_schedule has not been called");
+  if (max_iters < 0) return fail(FA_EINVAL, "max_iters must be >= 0");
+  fa_pair F = H->F, M = H->M;
+  int done = 0;
+  while (done < max_iters) {
+    FA_TRY(advance_levels(F));
+    FA_TRY(advance_levels(M));
+    if (schedule_done(M)) break;
+    const Level& LF = F->levels[F->cur_level];
+    const Level& LM = M->levels[M->cur_level];
+    const fa_shape& s = LM.shape;
+    // both warped images first: the two halves step from the same pair of warps
+    FA_HIP(fa::launch_warp(LF.moving, F->d, H->wf, s.n0, s.n1, s.n2, H->stream));
+    FA_HIP(fa::launch_warp(LM.moving, M->d, H->wm, s.n0, s.n1, s.n2, H->stream));
+    FA_TRY(launch_iteration(M, LM, H->wf));
+    FA_TRY(launch_iteration(F, LF, H->wm));
+    for (fa_pair P : {F, M}) {
+      P->cur_iter += 1;
+      P->t_done += 1;
+      P->iters_done += 1;
+    }
+    done += 1;
+  }
+  if (iters_done) *iters_done = done;
+  if (finished) *finished = schedule_done(M) ? 1 : 0;
+  return FA_OK;
+}
+
+fa_status fa_sym_get_halfway(fa_sym H, float* dF_dev, float* dM_dev, int* level, fa_shape* shape) {
+  if (!H) return fail(FA_EINVAL, "handle is NULL");
+  FA_TRY(fa_pair_get_field(H->F, dF_dev, 0, nullptr, nullptr));
+  return fa_pair_get_field(H->M, dM_dev, 0, level, shape);
+}
+
+fa_status fa_sym_get_loss(fa_sym H, float* host_out, int capacity, int* n_written) {
+  if (n_written) *n_written = 0;
+  if (!H) return fail(FA_EINVAL, "handle is NULL");
+  return fa_pair_get_loss(H->M, host_out, capacity, n_written);
+}
+
+fa_status fa_sym_finish(fa_sym H, const fa_params* inv_params, int n_levels, const float* scales,
+                        const int* iters, float* d_out, float* inv_cost) {
+  if (!H) return fail(FA_EINVAL, "handle is NULL");
+  if (!d_out) return fail(FA_EINVAL, "d_out is NULL");
+  if (!H->M->scheduled || !schedule_done(H->M) || !schedule_done(H->F))
+    return fail(FA_ESTATE, "the half-way schedule is not complete");
+  const Level& L = H->M->levels[H->M->cur_level];
+  if (L.shape.n0 != H->shape.n0 || L.shape.n1 != H->shape.n1 || L.shape.n2 != H->shape.n2)
+    return fail(FA_ESTATE, "the schedule's last level must be the input grid (scale 1)");
+  fa_inverse inv = nullptr;
+  FA_TRY(fa_inverse_create(H->F->d, H->shape, inv_params, H->stream, &inv));
+  fa_status st = fa_inverse_set_schedule(inv, n_levels, scales, iters);
+  if (st == FA_OK) st = fa_inverse_step(inv, 1 << 30, nullptr, nullptr);
+  int lvl = 0;
+  fa_shape es{};
+  if (st == FA_OK) st = fa_inverse_get_field(inv, nullptr, &lvl, &es);
+  if (st == FA_OK && (es.n0 != H->shape.n0 || es.n1 != H->shape.n1 || es.n2 != H->shape.n2))
+    st = fail(FA_EINVAL, "the inverse schedule's last level must be the input grid (scale 1)");
+  // e goes to pair M's scratch field (3 n floats, idle once the schedule is done)
+  float* e = H->M->tmp;
+  if (st == FA_OK) st = fa_inverse_get_field(inv, e, nullptr, nullptr);
+  if (st == FA_OK) {
+    const hipError_t he = fa::launch_compose_fields(e, H->M->d, d_out, H->shape.n0, H->shape.n1, H->shape.n2,
+                                                    H->stream);
+    if (he != hipSuccess) st = fail(FA_EHIP, std::string("compose: ") + hipGetErrorString(he));
+  }
+  if (st == FA_OK && inv_cost) {
+    int total = 0;
+    for (int i = 0; i < n_levels; ++i) total += iters[i];
+    std::vector<float> hist((size_t)std::max(total, 1));
+    int got = 0;
+    st = fa_inverse_get_loss(inv, hist.data(), total, &got);
+    *inv_cost = got > 0 ? hist[(size_t)got - 1] : 0.0f;
+  }
+  fa_inverse_destroy(inv);
+  if (st == FA_OK) {
+    const hipError_t he = hipStreamSynchronize(H->stream);
+    if (he != hipSuccess) st = fail(FA_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(he));
+  }
+  return st;
+}
+
+void fa_sym_destroy(fa_sym H) {
+  if (!H) return;
+  (void)hipStreamSynchronize(H->stream);
+  if (H->wf) (void)hipFree(H->wf);
+  if (H->wm) (void)hipFree(H->wm);
+  fa_pair_destroy(H->F);
+  fa_pair_destroy(H->M);
+  delete H;
 }
 
 }  // extern "C"

@@ -78,6 +78,13 @@ SIGNATURES = {
     "fa_inverse_eval_gradient": (_I, [_P, _P, _FP]),
     "fa_inverse_destroy": (None, [_P]),
     "fa_inverse_set_splat": (_I, [_P, _I]),
+    "fa_sym_create": (_I, [_P, _P, fa_shape, ctypes.POINTER(fa_params), _P, ctypes.POINTER(_P)]),
+    "fa_sym_set_schedule": (_I, [_P, _I, _FP, _IP]),
+    "fa_sym_step": (_I, [_P, _I, _IP, _IP]),
+    "fa_sym_get_halfway": (_I, [_P, _P, _P, _IP, ctypes.POINTER(fa_shape)]),
+    "fa_sym_get_loss": (_I, [_P, _FP, _I, _IP]),
+    "fa_sym_finish": (_I, [_P, ctypes.POINTER(fa_params), _I, _FP, _IP, _P, _FP]),
+    "fa_sym_destroy": (None, [_P]),
     "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
     "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "fa_lncc_destroy": (None, [_P]),
@@ -373,6 +380,59 @@ def fa_inverse_set_splat(h: int, direct: bool):
 def fa_inverse_destroy(h: int):
     if h:
         load_library().fa_inverse_destroy(h)
+
+
+def fa_sym_create(fixed, moving, params: fa_params, stream=None) -> int:
+    if fixed.shape != moving.shape or fixed.dim() != 3:
+        raise ValueError("fixed and moving must be 3-D volumes of the same shape")
+    shape = fa_shape(*[int(s) for s in fixed.shape])
+    h = _P()
+    _check(load_library().fa_sym_create(_ptr(fixed), _ptr(moving), shape, ctypes.byref(params),
+                                        _stream_handle(stream), ctypes.byref(h)))
+    return h.value
+
+
+def fa_sym_set_schedule(h: int, scales, iters):
+    scales = np.ascontiguousarray(scales, dtype=np.float32)
+    iters = np.ascontiguousarray(iters, dtype=np.int32)
+    if scales.shape != iters.shape or scales.ndim != 1:
+        raise ValueError("scales and iters must be 1-D of equal length")
+    _check(load_library().fa_sym_set_schedule(h, len(scales), scales.ctypes.data_as(_FP), iters.ctypes.data_as(_IP)))
+
+
+def fa_sym_step(h: int, max_iters: int) -> tuple[int, int]:
+    done, fin = ctypes.c_int(0), ctypes.c_int(0)
+    _check(load_library().fa_sym_step(h, int(max_iters), ctypes.byref(done), ctypes.byref(fin)))
+    return done.value, fin.value
+
+
+def fa_sym_get_halfway(h: int, dF=None, dM=None) -> tuple[int, tuple]:
+    lvl, shp = ctypes.c_int(0), fa_shape()
+    _check(load_library().fa_sym_get_halfway(h, _ptr(dF), _ptr(dM), ctypes.byref(lvl), ctypes.byref(shp)))
+    return lvl.value, (shp.n0, shp.n1, shp.n2)
+
+
+def fa_sym_get_loss(h: int, capacity: int) -> np.ndarray:
+    out = np.zeros(max(int(capacity), 0), dtype=np.float32)
+    n = ctypes.c_int(0)
+    _check(load_library().fa_sym_get_loss(h, out.ctypes.data_as(_FP), len(out), ctypes.byref(n)))
+    return out[: n.value]
+
+
+def fa_sym_finish(h: int, inv_params: fa_params, scales, iters, d_out) -> float:
+    scales = np.ascontiguousarray(scales, dtype=np.float32)
+    iters = np.ascontiguousarray(iters, dtype=np.int32)
+    if scales.shape != iters.shape or scales.ndim != 1:
+        raise ValueError("scales and iters must be 1-D of equal length")
+    cost = ctypes.c_float(0.0)
+    _check(load_library().fa_sym_finish(h, ctypes.byref(inv_params), len(scales), scales.ctypes.data_as(_FP),
+                                        iters.ctypes.data_as(_IP), _ptr(d_out), ctypes.byref(cost)))
+    return cost.value
+
+
+def fa_sym_destroy(h: int):
+    if h:
+        load_library().fa_sym_destroy(h)
 
 
 def fa_batch_step_fused(pairs, max_iters: int) -> int:

@@ -154,3 +154,17 @@ def test_inverse_rejects_bad_arguments_before_any_device_work(lib):
     assert lib.fa_inverse_eval_gradient(None, None, None) == fa.FA_EINVAL
     assert lib.fa_inverse_set_splat(None, 0) == fa.FA_EINVAL
     lib.fa_inverse_destroy(None)
+
+
+def test_symmetric_rejects_bad_arguments_before_any_device_work(lib):
+    p = fa.fa_params_default()
+    shp = fa.fa_shape(8, 9, 10)
+    h = ctypes.c_void_p(0)
+    assert lib.fa_sym_create(None, None, shp, ctypes.byref(p), None, ctypes.byref(h)) == fa.FA_EINVAL
+    assert lib.fa_sym_create(ctypes.c_void_p(16), ctypes.c_void_p(16), shp, ctypes.byref(p), None, None) == fa.FA_EINVAL
+    assert lib.fa_sym_set_schedule(None, 1, None, None) == fa.FA_EINVAL
+    assert lib.fa_sym_step(None, 1, None, None) == fa.FA_EINVAL
+    assert lib.fa_sym_get_halfway(None, None, None, None, None) == fa.FA_EINVAL
+    assert lib.fa_sym_get_loss(None, None, 0, None) == fa.FA_EINVAL
+    assert lib.fa_sym_finish(None, ctypes.byref(p), 1, None, None, None, None) == fa.FA_EINVAL
+    lib.fa_sym_destroy(None)
