@@ -18,8 +18,9 @@
  * asymmetric registration.
  *
  * All work runs on the handle's stream.  An iteration is two warps (each half's
- * image by its own warp), the two halves' fused gradient + Adam launches and
- * their smoothing and composition launches.
+ * image by its own warp), then the fused gradient + Adam, smoothing and
+ * composition kernels, each as one batched launch over both halves (the
+ * launches of fa_batch_step_fused).
  */
 #ifndef FA_SYMMETRIC_H_
 #define FA_SYMMETRIC_H_
@@ -46,7 +47,9 @@ fa_status fa_sym_create(const float* fixed, const float* moving, fa_shape shape,
 fa_status fa_sym_set_schedule(fa_sym h, int n_levels, const float* scales, const int* iters);
 
 /* Runs up to max_iters iterations of both halves.  *iters_done and *finished
- * (may be NULL) as fa_pair_step.  Enqueued.  FA_EINVAL, FA_ESTATE, FA_EHIP. */
+ * (may be NULL) as fa_pair_step.  Synchronises with the stream when the level
+ * changes (the batched launches' tables are uploaded then) and before it
+ * returns.  FA_EINVAL, FA_ESTATE, FA_ENOMEM, FA_EHIP. */
 fa_status fa_sym_step(fa_sym h, int max_iters, int* iters_done, int* finished);
 
 /* The half-way displacements d_F and d_M at the current level into dF_dev and

@@ -135,6 +135,9 @@ struct fa_pair_s {
   int t_done = 0;      // Adam steps taken (set_state may change it)
   int iters_done = 0;  // schedule iterations run = losses recorded
   bool scheduled = false;
+  // the fixed image of every iteration instead of the level's own (a half of
+  // the symmetric registration: the other half's warped image)
+  const float* fixed_override = nullptr;
 };
 
 namespace {
@@ -240,7 +243,7 @@ struct IterPlan {
 void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed = nullptr) {
   fa::GradArgs& ga = it.ga;
   ga = fa::GradArgs{};
-  ga.fixed = fixed ? fixed : L.fixed;
+  ga.fixed = fixed ? fixed : (P->fixed_override ? P->fixed_override : L.fixed);
   ga.moving_pad = L.moving_pad;
   ga.d = P->d;
   ga.m = P->m;
@@ -1278,26 +1281,48 @@ fa_status fa_sym_step(fa_sym H, int max_iters, int* iters_done, int* finished) {
   if (!H->F->scheduled || !H->M->scheduled) return fail(FA_ESTATE, "fa_sym_set_schedule has not been called");
   if (max_iters < 0) return fail(FA_EINVAL, "max_iters must be >= 0");
   fa_pair F = H->F, M = H->M;
+  M->fixed_override = H->wf;
+  F->fixed_override = H->wm;
+  // the two halves share every template parameter: each kernel of an
+  // iteration is one batched launch over both
+  const std::vector<fa_pair> both = {M, F};
+  BatchTables bt;
+  int level = -1;
   int done = 0;
-  while (done < max_iters) {
-    FA_TRY(advance_levels(F));
-    FA_TRY(advance_levels(M));
+  fa_status st = FA_OK;
+  while (done < max_iters && st == FA_OK) {
+    if ((st = advance_levels(F)) != FA_OK || (st = advance_levels(M)) != FA_OK) break;
     if (schedule_done(M)) break;
+    if (M->cur_level != level) {
+      if ((st = build_batch_tables(both, bt)) != FA_OK) break;
+      if ((st = upload_batch_tables(bt, H->stream)) != FA_OK) break;
+      level = M->cur_level;
+    }
     const Level& LF = F->levels[F->cur_level];
     const Level& LM = M->levels[M->cur_level];
     const fa_shape& s = LM.shape;
     // both warped images first: the two halves step from the same pair of warps
-    FA_HIP(fa::launch_warp(LF.moving, F->d, H->wf, s.n0, s.n1, s.n2, H->stream));
-    FA_HIP(fa::launch_warp(LM.moving, M->d, H->wm, s.n0, s.n1, s.n2, H->stream));
-    FA_TRY(launch_iteration(M, LM, H->wf));
-    FA_TRY(launch_iteration(F, LF, H->wm));
-    for (fa_pair P : {F, M}) {
+    hipError_t he = fa::launch_warp(LF.moving, F->d, H->wf, s.n0, s.n1, s.n2, H->stream);
+    if (he == hipSuccess) he = fa::launch_warp(LM.moving, M->d, H->wm, s.n0, s.n1, s.n2, H->stream);
+    if (he != hipSuccess) {
+      st = fail(FA_EHIP, std::string("warp: ") + hipGetErrorString(he));
+      break;
+    }
+    if ((st = launch_batch_iteration(both, bt, H->stream)) != FA_OK) break;
+    for (fa_pair P : both) {
       P->cur_iter += 1;
       P->t_done += 1;
       P->iters_done += 1;
     }
     done += 1;
   }
+  if (bt.dev) {
+    const hipError_t e1 = hipStreamSynchronize(H->stream);
+    const hipError_t e2 = hipFree(bt.dev);
+    if (st == FA_OK && e1 != hipSuccess) st = fail(FA_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e1));
+    if (st == FA_OK && e2 != hipSuccess) st = fail(FA_EHIP, std::string("hipFree: ") + hipGetErrorString(e2));
+  }
+  if (st != FA_OK) return st;
   if (iters_done) *iters_done = done;
   if (finished) *finished = schedule_done(M) ? 1 : 0;
   return FA_OK;
