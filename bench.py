@@ -412,7 +412,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the dense matching step of one registration is not "
-              "sharded across GPUs in this build (--gpus 1).", file=sys.stderr)
+              "sharded across GPUs (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
 

@@ -2,7 +2,7 @@
 
 Every case feeds the same seeded float32 inputs to the library and (promoted
 to float64) to the oracle, then compares element by element.  Tolerances
-(relative, as defined for this build):
+(relative, each defined as below):
 
 * warped intensity: max|dJ| / max|J|  <= 1e-5
 * loss:             |dL| / |L|        <= 1e-5
