@@ -25,6 +25,8 @@ Prints one JSON line.  Besides the headline value it reports
 * ``inverse``: the post hoc inverse of the result (psi = phi^{-1} fitted by
   the same loop on the inverse-consistency cost): time per fit and the final
   cost;
+* ``autotuned``: the same registration with launch shapes picked on this GPU
+  by fa_pair_autotune (tuning outside the timed region);
 * ``symmetric``: the symmetric registration (two half-way warps, then
   phi = phi_M o phi_F^{-1}): time per registration relative to the
   asymmetric one, and its accuracy;
@@ -184,6 +186,41 @@ def run_inverse(field, steps, params):
     loss = inv.loss_history()
     inv.close()
     return start.elapsed_time(end) / steps, vox, loss
+
+
+def run_autotuned(p, steps, params):
+    """The workload with the launch shapes picked by fa_pair_autotune on this
+    GPU (the best of three runs of 10 launches per candidate), tuned once; the timed registrations'
+    schedules take the kept shapes.  Returns milliseconds per registration
+    (HIP events, after a warm-up), the tuning time in seconds, the final loss
+    and the chosen shapes per level.  The kept shapes are cleared at the
+    end."""
+    import torch
+
+    from paper_2404_01249_amd import Pair
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    stream = torch.cuda.current_stream()
+    pr = Pair(fixed, moving, stream=stream, **params)
+    from paper_2404_01249_amd import fa
+    pr.set_schedule(p.scales, p.iters)
+    t0 = time.perf_counter()
+    pr.autotune(trials=10)
+    tune_s = time.perf_counter() - t0
+    pr.run()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        pr.set_schedule(p.scales, p.iters)
+        pr.run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    shapes = {f"level{l}": [list(pr.tiling(l, k)) for k in range(4)] for l in range(len(p.scales))}
+    loss = pr.loss_history()
+    pr.close()
+    fa.fa_autotune_clear()
+    return start.elapsed_time(end) / steps, tune_s, float(loss[-1]), shapes
 
 
 def run_symmetric(p, steps, params):
@@ -398,6 +435,8 @@ def main():
                     help="grid-search batch: skip the sequential comparison (for kernel traces)")
     ap.add_argument("--inverse-steps", type=int, default=2,
                     help="timed fits of the post hoc inverse of the result (0 skips)")
+    ap.add_argument("--tune-steps", type=int, default=2,
+                    help="timed registrations with autotuned launch shapes (0 skips)")
     ap.add_argument("--sym-steps", type=int, default=2,
                     help="timed symmetric registrations (0 skips)")
     ap.add_argument("--jac-steps", type=int, default=2,
@@ -503,6 +542,10 @@ def main():
                           "schedule": "scales [4.0, 2.0, 1.0] at [100, 50, 25], eta 0.2",
                           "cost_first": float(iloss[0]), "cost_final": float(iloss[-1]),
                           "rms_residual_final": float(np.sqrt(iloss[-1] / 2.0))}
+    if args.tune_steps > 0:
+        tms, tune_s, tloss, shapes = run_autotuned(p, args.tune_steps, params)
+        out["autotuned"] = {"ms_per_step": tms, "speedup": ms / tms, "tuning_s": tune_s, "final_loss": tloss,
+                            "shapes_ty_tx_zc_brick": shapes}
     if args.sym_steps > 0:
         sms, sloss, sfield = run_symmetric(p, args.sym_steps, params)
         out["symmetric"] = {"ms_per_step": sms, "runtime_ratio": sms / ms, "final_halfway_loss": float(sloss[-1]),

@@ -75,6 +75,35 @@ fa_status fa_pair_get_profile(fa_pair pair, int level, int kind, double* total_m
  * the launch shape beyond floating-point summation order. */
 fa_status fa_pair_set_tuning(fa_pair pair, int kind, int ty, int tx, int zc, int variant);
 
+/* A launch-shape autotuner: for every level of the schedule and each of the
+ * four kernels (kinds as in fa_pair_set_tuning), times candidate launch shapes
+ * on this GPU and keeps the fastest for that level.  Candidates: the automatic
+ * shape; the 16x32 and 8x32 tiles (8x64 too for kinds 1 to 3) at chunk
+ * lengths giving 1/2, 2/3, 1, 3/2 and 2 times their automatic number of
+ * chunks; bricks where they exist, for volumes up to 1.2 M voxels.  Each is
+ * timed with HIP events, as the fastest of three runs of `trials` launches
+ * (in [1, 100]) after one warm-up, on the level's images with every output, the Adam moments and the
+ * control block redirected to scratch: the pair's state (d, m, v, step
+ * count, loss history) is unchanged.  Batched launches keep tuned chunks.
+ * Call after fa_pair_set_schedule.  The choices are also kept for the
+ * process, per device, kernel, level grid and kernel form (window, Gaussian
+ * radius, composition form): every later fa_pair_set_schedule with such a
+ * level uses them unless fa_pair_set_tuning overrides that kernel, so one
+ * call tunes all later registrations of those shapes.  Synchronises.  Results do not depend on the shapes beyond floating-point
+ * summation order (bricks sum the gradient's window statistics in another
+ * order).  FA_EINVAL, FA_ESTATE (no schedule), FA_ENOMEM, FA_EHIP. */
+fa_status fa_pair_autotune(fa_pair pair, int trials);
+
+/* Forgets every launch shape fa_pair_autotune has kept for the process
+ * (pairs already scheduled keep theirs). */
+void fa_autotune_clear(void);
+
+/* The launch shape in use for kernel `kind` (as in fa_pair_set_tuning) at
+ * `level`: in-plane tile ty x tx, planes per workgroup zc, and whether it is a
+ * brick launch (*brick = 1; then ty, tx, zc are the brick's extents).  Any
+ * output may be NULL.  FA_EINVAL, FA_ESTATE. */
+fa_status fa_pair_get_tiling(fa_pair pair, int level, int kind, int* ty, int* tx, int* zc, int* brick);
+
 /* Host-only view of the automatic march launch shapes (no GPU involved).
  * kind as in fa_pair_set_tuning; shapes: n volumes (host array).
  * batched = 0: each volume's own launch (the chunk fa_pair_step uses);

@@ -55,6 +55,16 @@ class Pair:
     def step(self, n):
         return fa.fa_pair_step(self.handle, n)
 
+    def autotune(self, trials=5):
+        """Time candidate launch shapes per level and kernel; keep the fastest
+        (after set_schedule; the state is unchanged)."""
+        fa.fa_pair_autotune(self.handle, trials)
+
+    def tiling(self, level, kind):
+        """(ty, tx, zc, brick) of kernel `kind` (0 gradient, 1 sigma_grad
+        smoothing, 2 sigma_warp smoothing, 3 composition) at `level`."""
+        return fa.fa_pair_get_tiling(self.handle, level, kind)
+
     def run(self):
         done, fin = fa.fa_pair_step(self.handle, 1 << 30)
         return done

@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -90,7 +93,22 @@ struct Level {
   float* moving_pad = nullptr;  // moving with a zero border (owned), sampled by the gradient kernel
   bool owns = false;
   Tiling tg{}, tsg{}, tsc{}, tsw{};  // gradient, sigma_grad, composition and sigma_warp launches
+  bool tuned[4] = {false, false, false, false};  // set by fa_pair_autotune (by KernelKind)
 };
+
+// Launch shapes chosen by fa_pair_autotune, per device, kernel kind, level
+// grid and the parameter that selects the kernel's form (window, Gaussian
+// radius, or whether the composition stages d in LDS).  Later schedules reuse
+// them.
+using TuneKey = std::tuple<int, int, int, int, int, int>;   // device, kind, n0, n1, n2, form
+std::map<TuneKey, Tiling>& tune_cache() {
+  static std::map<TuneKey, Tiling> m;
+  return m;
+}
+std::mutex& tune_mutex() {
+  static std::mutex mu;
+  return mu;
+}
 
 }  // namespace
 
@@ -141,6 +159,16 @@ struct fa_pair_s {
 };
 
 namespace {
+
+// The parameter that selects kernel `kind`'s form (key of the tuned-shape cache).
+int tune_form(const fa_pair P, int kind) {
+  switch (kind) {
+    case fa::KIND_GRAD: return P->p.cc_window;
+    case fa::KIND_SMOOTH_MAX: return tap_radius(P->p.sigma_grad);
+    case fa::KIND_WARP_SMOOTH: return tap_radius(P->p.sigma_warp);
+    default: return P->p.eta <= 2.0f ? 1 : 0;
+  }
+}
 
 void free_levels(fa_pair P) {
   for (auto& L : P->levels) {
@@ -475,7 +503,8 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
     for (size_t j : mem) {
       ts.push_back(&its[j].tg);
       n0s.push_back(its[j].ga.n0);
-      pinned.push_back(live[j]->tune[fa::KIND_GRAD].zc > 0);
+      pinned.push_back(live[j]->tune[fa::KIND_GRAD].zc > 0 ||
+                       live[j]->levels[live[j]->cur_level].tuned[fa::KIND_GRAD]);
     }
     std::vector<Tiling> orig;
     for (size_t j : mem) orig.push_back(its[j].tg);
@@ -515,7 +544,7 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
       for (size_t j : mem) {
         ts.push_back(&its[j].tgs[k]);
         n0s.push_back(its[j].g[k].n0);
-        pinned.push_back(live[j]->tune[kinds[k]].zc > 0);
+        pinned.push_back(live[j]->tune[kinds[k]].zc > 0 || live[j]->levels[live[j]->cur_level].tuned[kinds[k]]);
       }
       // halo planes: 2R of the smoothing, one plane ahead for the composition
       fa::batch_chunks(kinds[k], k == 1 ? 2 : 2 * its[i].radius[k], ts, n0s, pinned);
@@ -826,6 +855,21 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
                               fa::gauss_cube_supported(P->rw, fa::EPI_STORE_FINAL));
     lv[i].tsc = choose_tiling(lv[i].shape, fa::KIND_COMPOSE, P->tune[3],
                               P->p.eta <= 2.0f && fa::gauss_cube_supported(0, fa::EPI_COMPOSE_LDS));
+    {
+      // shapes tuned earlier in this process for this grid and form (unless overridden)
+      std::lock_guard<std::mutex> lk(tune_mutex());
+      Tiling* slots[4] = {&lv[i].tg, &lv[i].tsg, &lv[i].tsw, &lv[i].tsc};
+      for (int k = 0; k < 4; ++k) {
+        const fa::Tuning& tu = P->tune[k];
+        if (tu.ty || tu.tx || tu.zc || tu.variant) continue;
+        auto it = tune_cache().find(TuneKey(P->device, k, lv[i].shape.n0, lv[i].shape.n1, lv[i].shape.n2,
+                                            tune_form(P, k)));
+        if (it != tune_cache().end()) {
+          *slots[k] = it->second;
+          lv[i].tuned[k] = true;
+        }
+      }
+    }
     total_iters += iters[i];
     nmax = std::max(nmax, lv[i].n);
     pmax = std::max(pmax, lv[i].tg.blocks());
@@ -1214,6 +1258,198 @@ fa_status fa_pair_get_profile(fa_pair P, int level, int kind, double* total_ms, 
   const size_t slot = (size_t)level * 4 + kind;
   if (total_ms) *total_ms = slot < P->prof_ms.size() ? P->prof_ms[slot] : 0.0;
   if (launches) *launches = slot < P->prof_n.size() ? P->prof_n[slot] : 0;
+  return FA_OK;
+}
+
+// ---- fa_pair_autotune ---------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// Candidate march tilings of kernel `kind` at shape s around the automatic
+// one: both in-plane tiles (8x64 too for the smoothing kinds), and chunk
+// lengths giving 1/2, 2/3, 1, 3/2 and 2 times the automatic number of chunks;
+// plus the brick form where it exists and the volume is small enough for it
+// to have a chance.
+std::vector<Tiling> tiling_candidates(const fa_shape& s, fa::KernelKind kind, const Tiling& t0, bool cube_ok) {
+  std::vector<Tiling> out;
+  auto add = [&](const Tiling& t) {
+    for (const Tiling& u : out)
+      if (u.cube == t.cube && u.ty == t.ty && u.tx == t.tx && u.zc == t.zc) return;
+    out.push_back(t);
+  };
+  add(t0);
+  std::vector<std::pair<int, int>> tiles = {{16, 32}, {8, 32}};
+  if (kind != fa::KIND_GRAD) tiles.push_back({8, 64});
+  for (auto [ty, tx] : tiles) {
+    if (ty == 16 && s.n1 < 16) continue;
+    fa::Tuning tu;
+    tu.ty = ty;
+    tu.tx = tx;
+    tu.variant = 1;
+    const Tiling base = choose_tiling(s, kind, tu, false);
+    const int chunks0 = base.chunks;
+    for (int num_den : {12, 23, 11, 32, 21}) {   // chunk-count factors 1/2, 2/3, 1, 3/2, 2
+      const int num = num_den / 10, den = num_den % 10;
+      const int ch = std::max(1, (chunks0 * num + den - 1) / den);
+      fa::Tuning tz = tu;
+      tz.zc = std::max(1, (s.n0 + ch - 1) / ch);
+      add(choose_tiling(s, kind, tz, false));
+    }
+  }
+  if (cube_ok && voxels(s) <= 1200000) {
+    fa::Tuning tc;
+    tc.variant = kind == fa::KIND_GRAD ? 3 : 2;
+    add(choose_tiling(s, kind, tc, true));
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+fa_status fa_pair_autotune(fa_pair P, int trials) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  if (trials < 1 || trials > 100) return fail(FA_EINVAL, "trials must be in [1, 100]");
+  FA_HIP(hipStreamSynchronize(P->stream));
+  // scratch control block: the timing launches update M, the ticket and the step count there
+  Ctl* sctl = nullptr;
+  FA_TRY(dalloc(&sctl, 1, "scratch control block"));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  fa_status st = FA_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    st = fail(FA_EHIP, "hipEventCreate failed");
+  // the fastest of three timed runs of `trials` launches each, after a warm-up
+  auto time_it = [&](auto&& launch, double* us) -> fa_status {
+    FA_HIP(launch());
+    *us = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      FA_HIP(hipEventRecord(e0, P->stream));
+      for (int r = 0; r < trials; ++r) FA_HIP(launch());
+      FA_HIP(hipEventRecord(e1, P->stream));
+      FA_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      FA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      *us = std::min(*us, 1e3 * ms / trials);
+    }
+    return FA_OK;
+  };
+  if (st == FA_OK) {
+    const hipError_t he = fa::launch_ctl_init(sctl, P->p.adam_beta1, P->p.adam_beta2, 0, 0, P->stream);
+    if (he != hipSuccess) st = fail(FA_EHIP, hipGetErrorString(he));
+  }
+  for (size_t li = 0; li < P->levels.size() && st == FA_OK; ++li) {
+    Level& L = P->levels[li];
+    const int w = P->p.cc_window;
+    // the gradient: mode 0 with m, v and the direction all in the scratch buffer tmp
+    std::vector<Tiling> cg = tiling_candidates(L.shape, fa::KIND_GRAD, L.tg, fa::grad_cube_supported(w));
+    int need = 0;
+    for (const Tiling& t : cg) need = std::max(need, t.blocks());
+    if (need > P->partials_cap) {
+      if (P->partials) (void)hipFree(P->partials);
+      P->partials = nullptr;
+      P->partials_cap = 0;
+      if ((st = dalloc(&P->partials, (size_t)need, "loss partials")) != FA_OK) break;
+      P->partials_cap = need;
+    }
+    IterPlan it;
+    plan_iteration(P, L, it);
+    fa::GradArgs ga = it.ga;
+    ga.m = ga.v = ga.out = P->tmp;
+    ga.ctl = sctl;
+    ga.mode = 0;
+    double best = 1e30;
+    Tiling bt = L.tg;
+    for (const Tiling& t : cg) {
+      fa::GradArgs a = ga;
+      a.zc = t.zc;
+      a.tiles_y = t.tiles_y;
+      a.tiles_x = t.tiles_x;
+      double us = 0.0;
+      if ((st = time_it([&]() { return fa::launch_grad(a, w, t, P->stream); }, &us)) != FA_OK) break;
+      if (us < best) {
+        best = us;
+        bt = t;
+      }
+    }
+    if (st != FA_OK) break;
+    L.tg = bt;
+    L.tuned[fa::KIND_GRAD] = true;
+    {
+      std::lock_guard<std::mutex> lk(tune_mutex());
+      tune_cache()[TuneKey(P->device, fa::KIND_GRAD, L.shape.n0, L.shape.n1, L.shape.n2,
+                           tune_form(P, fa::KIND_GRAD))] = bt;
+    }
+    // the smoothing and composition launches, on scratch buffers a and tmp
+    const fa::KernelKind kinds[3] = {fa::KIND_SMOOTH_MAX, fa::KIND_COMPOSE, fa::KIND_WARP_SMOOTH};
+    Tiling* slots[3] = {&L.tsg, &L.tsc, &L.tsw};
+    for (int k = 0; k < 3 && st == FA_OK; ++k) {
+      const bool cube_ok = k == 0   ? fa::gauss_cube_supported(P->rg, fa::EPI_SMOOTH_MAX)
+                           : k == 1 ? (P->p.eta <= 2.0f && fa::gauss_cube_supported(0, fa::EPI_COMPOSE_LDS))
+                                    : fa::gauss_cube_supported(P->rw, fa::EPI_STORE_FINAL);
+      std::vector<Tiling> cs = tiling_candidates(L.shape, kinds[k], *slots[k], cube_ok);
+      fa::GaussArgs g = it.g[k];
+      g.ctl = sctl;
+      if (k == 0) {
+        g.in = P->a;
+        g.out = P->tmp;
+      } else if (k == 1) {
+        g.in = g.out = P->tmp;
+      } else {
+        g.in = P->tmp;
+        g.out = P->a;
+        g.loss_hist = nullptr;
+        g.n_partials = std::min(L.tg.blocks(), P->partials_cap);
+      }
+      double bestk = 1e30;
+      Tiling btk = *slots[k];
+      for (const Tiling& t : cs) {
+        fa::GaussArgs a = g;
+        a.zc = t.zc;
+        a.tiles_y = t.tiles_y;
+        a.tiles_x = t.tiles_x;
+        double us = 0.0;
+        if ((st = time_it([&]() { return fa::launch_gauss(a, it.radius[k], it.epi[k], t, P->stream); }, &us)) != FA_OK)
+          break;
+        if (us < bestk) {
+          bestk = us;
+          btk = t;
+        }
+      }
+      if (st == FA_OK) {
+        *slots[k] = btk;
+        L.tuned[kinds[k]] = true;
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        tune_cache()[TuneKey(P->device, kinds[k], L.shape.n0, L.shape.n1, L.shape.n2, tune_form(P, kinds[k]))] = btk;
+      }
+    }
+  }
+  (void)hipStreamSynchronize(P->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(sctl);
+  return st;
+}
+
+void fa_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  tune_cache().clear();
+}
+
+fa_status fa_pair_get_tiling(fa_pair P, int level, int kind, int* ty, int* tx, int* zc, int* brick) {
+  if (!P) return fail(FA_EINVAL, "pair is NULL");
+  if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
+  if (level < 0 || level >= (int)P->levels.size()) return fail(FA_EINVAL, "level out of range");
+  if (kind < 0 || kind > 3) return fail(FA_EINVAL, "kind must be in [0, 3]");
+  const Level& L = P->levels[level];
+  const Tiling& t = kind == 0 ? L.tg : kind == 1 ? L.tsg : kind == 2 ? L.tsw : L.tsc;
+  if (ty) *ty = t.ty;
+  if (tx) *tx = t.tx;
+  if (zc) *zc = t.zc;
+  if (brick) *brick = t.cube ? 1 : 0;
   return FA_OK;
 }
 

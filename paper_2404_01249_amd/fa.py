@@ -70,6 +70,9 @@ SIGNATURES = {
     "fa_batch_step": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
     "fa_batch_step_fused": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
     "fa_plan_tiling": (_I, [_I, _I, ctypes.POINTER(fa_shape), _I, _I, _IP, _IP]),
+    "fa_pair_autotune": (_I, [_P, _I]),
+    "fa_pair_get_tiling": (_I, [_P, _I, _I, _IP, _IP, _IP, _IP]),
+    "fa_autotune_clear": (None, []),
     "fa_inverse_create": (_I, [_P, fa_shape, ctypes.POINTER(fa_params), _P, ctypes.POINTER(_P)]),
     "fa_inverse_set_schedule": (_I, [_P, _I, _FP, _IP]),
     "fa_inverse_step": (_I, [_P, _I, _IP, _IP]),
@@ -316,6 +319,21 @@ def fa_batch_step(pairs, max_iters: int) -> int:
     fin = ctypes.c_int(0)
     _check(load_library().fa_batch_step(arr, len(pairs), int(max_iters), ctypes.byref(fin)))
     return fin.value
+
+
+def fa_pair_autotune(pair: int, trials: int = 5):
+    _check(load_library().fa_pair_autotune(pair, int(trials)))
+
+
+def fa_autotune_clear():
+    load_library().fa_autotune_clear()
+
+
+def fa_pair_get_tiling(pair: int, level: int, kind: int) -> tuple[int, int, int, bool]:
+    ty, tx, zc, br = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _check(load_library().fa_pair_get_tiling(pair, int(level), int(kind), ctypes.byref(ty), ctypes.byref(tx),
+                                             ctypes.byref(zc), ctypes.byref(br)))
+    return ty.value, tx.value, zc.value, bool(br.value)
 
 
 def fa_plan_tiling(kind: int, shapes, halo: int, batched: bool):

@@ -168,3 +168,8 @@ def test_symmetric_rejects_bad_arguments_before_any_device_work(lib):
     assert lib.fa_sym_get_loss(None, None, 0, None) == fa.FA_EINVAL
     assert lib.fa_sym_finish(None, ctypes.byref(p), 1, None, None, None, None) == fa.FA_EINVAL
     lib.fa_sym_destroy(None)
+
+
+def test_autotune_rejects_bad_arguments(lib):
+    assert lib.fa_pair_autotune(None, 5) == fa.FA_EINVAL
+    assert lib.fa_pair_get_tiling(None, 0, 0, None, None, None, None) == fa.FA_EINVAL

@@ -424,3 +424,50 @@ def test_step_before_schedule_is_a_state_error():
     assert pr.step(5) == (2, 1)
     assert pr.step(5) == (0, 1)
     pr.close()
+
+
+def test_autotune_keeps_state_and_results():
+    """The autotuner times launch shapes on scratch outputs: the pair's state
+    is unchanged, every chosen shape is a valid one, and the run that follows
+    matches an untuned run (to summation order, as bricks may be chosen)."""
+    fixed, moving, _ = make_problem((40, 48, 56), seed=91)
+    ref = new_pair(fixed, moving)
+    ref.set_schedule([2.0, 1.0], [8, 6])
+    ref.run()
+    ref_loss, ref_d = ref.loss_history(), host(ref.field())
+    ref.close()
+    try:
+        _autotune_checks(fixed, moving, ref_loss, ref_d)
+    finally:
+        fa.fa_autotune_clear()   # the kept shapes are process-wide
+
+
+def _autotune_checks(fixed, moving, ref_loss, ref_d):
+    pr = new_pair(fixed, moving)
+    pr.set_schedule([2.0, 1.0], [8, 6])
+    pr.autotune(trials=2)
+    d0, m0, v0 = (host(t) for t in pr.state())
+    assert not d0.any() and not m0.any() and not v0.any()
+    assert pr.progress() == (0, 0, 0)
+    for level in (0, 1):
+        for kind in range(4):
+            ty, tx, zc, brick = pr.tiling(level, kind)
+            assert (ty, tx) in ((16, 32), (8, 32), (8, 64), (8, 16)) and zc >= 1
+    assert pr.run() == 14
+    loss, d = pr.loss_history(), host(pr.field())
+    tuned = [[pr.tiling(level, kind) for kind in range(4)] for level in (0, 1)]
+    pr.close()
+    np.testing.assert_allclose(loss, ref_loss, rtol=1e-4)
+    assert np.sqrt(((d - ref_d) ** 2).sum(0)).mean() <= 1e-3
+    # later schedules of the same level grids reuse the tuned shapes, until cleared
+    q = new_pair(fixed, moving)
+    q.set_schedule([2.0, 1.0], [1, 1])
+    assert [[q.tiling(level, kind) for kind in range(4)] for level in (0, 1)] == tuned
+    fa.fa_autotune_clear()
+    q.set_schedule([2.0, 1.0], [1, 1])
+    auto = [[q.tiling(level, kind) for kind in range(4)] for level in (0, 1)]
+    q.close()
+    u = new_pair(fixed, moving)
+    u.set_schedule([2.0, 1.0], [1, 1])
+    assert [[u.tiling(level, kind) for kind in range(4)] for level in (0, 1)] == auto
+    u.close()
