@@ -345,8 +345,15 @@ def run_grid_search(n_variants, params, sequential_too=True):
         run_batch(pairs, fused=True)
         torch.cuda.synchronize()
 
+    def fused_graphs():
+        for pr in pairs:
+            pr.set_schedule(scales, iters)
+        run_batch(pairs, fused=True, graphs=True)
+        torch.cuda.synchronize()
+
     out = {"registrations": len(pairs), "voxel_iters": vox_iters}
-    forms = (("sequential", sequential), ("fused", fused)) if sequential_too else (("fused", fused),)
+    forms = (("sequential", sequential), ("fused", fused), ("fused_graphs", fused_graphs)) if sequential_too \
+        else (("fused", fused),)
     for name, fn in forms:
         fn()
         t0 = time.perf_counter()
@@ -533,6 +540,7 @@ def main():
             "fused_s": g["fused"], "fused_voxel_iters_per_s": g["voxel_iters"] / g["fused"]}
         if "sequential" in g:
             out["grid_search"].update({
+                "fused_graphs_s": g["fused_graphs"],
                 "sequential_s": g["sequential"],
                 "sequential_voxel_iters_per_s": g["voxel_iters"] / g["sequential"],
                 "fused_speedup": g["sequential"] / g["fused"]})

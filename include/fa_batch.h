@@ -51,6 +51,16 @@ fa_status fa_batch_step(fa_pair* pairs, int n, int max_iters, int* n_finished);
  * already advanced keep their progress. */
 fa_status fa_batch_step_fused(fa_pair* pairs, int n, int max_iters, int* n_finished);
 
+/* Process-wide switch for fa_batch_step_fused (off by default).  On: the call
+ * runs on a private non-blocking stream (joined to the pairs' streams by
+ * events at entry and exit); the first iteration of each batch composition
+ * runs eagerly, its launches are then captured once into a HIP graph, and the
+ * graph replays every later iteration until the composition changes.  The
+ * iteration's per-step values live in the pairs' control blocks on the
+ * device, so a replay needs no host input.  Results are those of the eager
+ * form. */
+void fa_batch_use_graphs(int enable);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,14 +14,20 @@ from .lncc import LNCC
 __all__ = ["Pair", "Inverse", "Symmetric", "FAError", "fa", "LNCC", "evaluate", "run_batch"]
 
 
-def run_batch(pairs, max_iters=1 << 30, fused=True):
+def run_batch(pairs, max_iters=1 << 30, fused=True, graphs=False):
     """Advance several :class:`Pair` objects together.  fused=True
     (fa_batch_step_fused): one launch per kernel for all pairs that share its
-    template parameters.  fused=False (fa_batch_step): each pair on its own
-    stream, interleaved.  Returns the number of pairs whose schedule is
-    complete."""
-    fn = fa.fa_batch_step_fused if fused else fa.fa_batch_step
-    return fn([p.handle for p in pairs], max_iters)
+    template parameters; graphs=True replays each batch composition's
+    iteration from a captured HIP graph.  fused=False (fa_batch_step): each
+    pair on its own stream, interleaved.  Returns the number of pairs whose
+    schedule is complete."""
+    if not fused:
+        return fa.fa_batch_step([p.handle for p in pairs], max_iters)
+    fa.fa_batch_use_graphs(graphs)
+    try:
+        return fa.fa_batch_step_fused([p.handle for p in pairs], max_iters)
+    finally:
+        fa.fa_batch_use_graphs(False)
 
 
 class Pair:

@@ -617,9 +617,18 @@ int count_finished(fa_pair* pairs, int n) {
   return f;
 }
 
-// The fused batch proper, with every pair's work on stream s.
+// Whether fa_batch_step_fused replays captured HIP graphs (fa_batch_use_graphs).
+bool g_batch_graphs = false;
+
+// The fused batch proper, with every pair's work on stream s.  With graphs:
+// the first iteration of each batch composition runs eagerly, then its
+// launches are captured once and the graph replays every later iteration
+// until the composition changes (nothing in an iteration depends on host
+// values that change between iterations).
 fa_status run_batch_fused(fa_pair* pairs, int n, int max_iters, hipStream_t s) {
   BatchTables bt;
+  hipGraphExec_t gexec = nullptr;
+  bool capture_next = false;
   std::vector<char> alive(n, 1);
   std::vector<std::pair<int, int>> sig, last;
   std::vector<fa_pair> live;
@@ -640,11 +649,46 @@ fa_status run_batch_fused(fa_pair* pairs, int n, int max_iters, hipStream_t s) {
     }
     if (st != FA_OK || live.empty()) break;
     if (sig != last) {
+      if (gexec) {
+        // the replays already queued use the old tables: upload_batch_tables synchronises first
+        (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+      }
       if ((st = build_batch_tables(live, bt)) != FA_OK) break;
       if ((st = upload_batch_tables(bt, s)) != FA_OK) break;
       last = sig;
+      capture_next = g_batch_graphs;
     }
-    if ((st = launch_batch_iteration(live, bt, s)) != FA_OK) break;
+    if (gexec) {
+      const hipError_t he = hipGraphLaunch(gexec, s);
+      if (he != hipSuccess) {
+        st = fail(FA_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(he));
+        break;
+      }
+    } else {
+      if ((st = launch_batch_iteration(live, bt, s)) != FA_OK) break;
+      if (capture_next) {
+        capture_next = false;
+        hipGraph_t graph = nullptr;
+        hipError_t he = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (he == hipSuccess) {
+          const fa_status cst = launch_batch_iteration(live, bt, s);
+          he = hipStreamEndCapture(s, &graph);
+          if (cst != FA_OK) {
+            st = cst;
+            if (graph) (void)hipGraphDestroy(graph);
+            break;
+          }
+        }
+        if (he == hipSuccess) he = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (he != hipSuccess) {
+          gexec = nullptr;
+          st = fail(FA_EHIP, std::string("capturing the batched iteration: ") + hipGetErrorString(he));
+          break;
+        }
+      }
+    }
     for (fa_pair P : live) {
       P->cur_iter += 1;
       P->t_done += 1;
@@ -658,6 +702,7 @@ fa_status run_batch_fused(fa_pair* pairs, int n, int max_iters, hipStream_t s) {
     if (st == FA_OK && e1 != hipSuccess) st = fail(FA_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e1));
     if (st == FA_OK && e2 != hipSuccess) st = fail(FA_EHIP, std::string("hipFree: ") + hipGetErrorString(e2));
   }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
   return st;
 }
 
@@ -1016,22 +1061,30 @@ fa_status fa_batch_step(fa_pair* pairs, int n, int max_iters, int* n_finished) {
   return FA_OK;
 }
 
+void fa_batch_use_graphs(int enable) { g_batch_graphs = enable != 0; }
+
 fa_status fa_batch_step_fused(fa_pair* pairs, int n, int max_iters, int* n_finished) {
   if (n_finished) *n_finished = 0;
   FA_TRY(check_batch(pairs, n, max_iters));
   for (int i = 1; i < n; ++i)
     if (pairs[i]->device != pairs[0]->device) return fail(FA_EINVAL, "the pairs of a batch must share a device");
   if (n > 0 && max_iters > 0) {
-    // Every pair's work goes to pairs[0]'s stream for the duration of the
-    // call; the stream first waits for the others' queued work, and they
-    // wait for it at the end.
-    const hipStream_t s = pairs[0]->stream;
+    // Every pair's work goes to one stream for the duration of the call:
+    // pairs[0]'s, or with graphs a private one (the default stream cannot be
+    // captured).  That stream first waits for the pairs' queued work, and
+    // their streams wait for it at the end.
+    hipStream_t priv = nullptr;
+    if (g_batch_graphs) FA_HIP(hipStreamCreateWithFlags(&priv, hipStreamNonBlocking));
+    const hipStream_t s = priv ? priv : pairs[0]->stream;
     std::vector<hipStream_t> saved(n);
     std::vector<hipEvent_t> evs;
     fa_status st = FA_OK;
     for (int i = 0; i < n && st == FA_OK; ++i) {
       saved[i] = pairs[i]->stream;
       if (saved[i] == s) continue;
+      bool seen = false;   // join each distinct stream once
+      for (int j = 0; j < i; ++j) seen |= saved[j] == saved[i];
+      if (seen) continue;
       hipEvent_t e = nullptr;
       hipError_t he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
       if (he == hipSuccess) {
@@ -1054,6 +1107,7 @@ fa_status fa_batch_step_fused(fa_pair* pairs, int n, int max_iters, int* n_finis
           if (saved[i] != s) (void)hipStreamWaitEvent(saved[i], done, 0);
     }
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (priv) (void)hipStreamDestroy(priv);   // its queued work still completes
     if (st != FA_OK) return st;
   }
   if (n_finished) *n_finished = count_finished(pairs, n);

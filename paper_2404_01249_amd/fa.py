@@ -69,6 +69,7 @@ SIGNATURES = {
     "fa_pair_get_profile": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_double), _IP]),
     "fa_batch_step": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
     "fa_batch_step_fused": (_I, [ctypes.POINTER(_P), _I, _I, _IP]),
+    "fa_batch_use_graphs": (None, [_I]),
     "fa_plan_tiling": (_I, [_I, _I, ctypes.POINTER(fa_shape), _I, _I, _IP, _IP]),
     "fa_pair_autotune": (_I, [_P, _I]),
     "fa_pair_get_tiling": (_I, [_P, _I, _I, _IP, _IP, _IP, _IP]),
@@ -451,6 +452,10 @@ def fa_sym_finish(h: int, inv_params: fa_params, scales, iters, d_out) -> float:
 def fa_sym_destroy(h: int):
     if h:
         load_library().fa_sym_destroy(h)
+
+
+def fa_batch_use_graphs(enable: bool):
+    load_library().fa_batch_use_graphs(int(bool(enable)))
 
 
 def fa_batch_step_fused(pairs, max_iters: int) -> int:

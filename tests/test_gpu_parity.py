@@ -367,13 +367,16 @@ def test_batched_pairs_match_single_runs(fused):
         pr.close()
 
 
-def test_fused_batch_of_uneven_pairs_matches_single_runs():
+@pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graphs"])
+def test_fused_batch_of_uneven_pairs_matches_single_runs(graphs):
     """Batched launches over pairs that differ in size (brick and march
     launches, 16x32 and 8x32 tiles), window, step size (eta = 3 takes the
     composition with gathers), smoothing, schedule and use_jac, advanced a few
     iterations per call so that the launch tables change as pairs change
     level or finish: every pair gives the field of its run alone, bitwise
-    (each voxel's arithmetic does not depend on the launch shape)."""
+    (each voxel's arithmetic does not depend on the launch shape).  With
+    graphs, the first iteration of each call runs eagerly and the other two
+    replay the captured graph, between the calls' own eager work."""
     from paper_2404_01249_amd import run_batch
     problems = [make_problem((21, 37, 45), seed=73), make_problem((40, 48, 56), seed=74),
                 make_problem((30, 12, 50), seed=75)]
@@ -401,7 +404,7 @@ def test_fused_batch_of_uneven_pairs_matches_single_runs():
         pairs.append(pr)
     calls, fin = 0, 0
     while fin < len(pairs):
-        fin = run_batch(pairs, 3, fused=True)
+        fin = run_batch(pairs, 3, fused=True, graphs=graphs)
         calls += 1
         assert calls <= 10
     for i, (pr, (loss, field)) in enumerate(zip(pairs, ref)):
