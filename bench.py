@@ -25,6 +25,8 @@ Prints one JSON line.  Besides the headline value it reports
 * ``inverse``: the post hoc inverse of the result (psi = phi^{-1} fitted by
   the same loop on the inverse-consistency cost): time per fit and the final
   cost;
+* ``microscopy512``: the 512^3 microscopy-like workload (LNCC 7^3, four
+  levels): time per registration and the per-level kernel split;
 * ``autotuned``: the same registration with launch shapes picked on this GPU
   by fa_pair_autotune (tuning outside the timed region);
 * ``symmetric``: the symmetric registration (two half-way warps, then
@@ -221,6 +223,69 @@ def run_autotuned(p, steps, params):
     pr.close()
     fa.fa_autotune_clear()
     return start.elapsed_time(end) / steps, tune_s, float(loss[-1]), shapes
+
+
+def run_microscopy512(steps, params):
+    """The 512^3 microscopy-like workload (synth.microscopy_pair, seed 5):
+    LNCC 7^3 over scales 8, 4, 2, 1 at 200, 200, 100, 50 iterations.  Returns
+    milliseconds per registration (HIP events, after a warm-up), the
+    voxel-iterations of one registration, the first and last loss, the
+    generation time, the per-level kernel split (HIP events, one more
+    registration) and the milliseconds per registration with launch shapes
+    from fa_pair_autotune."""
+    import torch
+
+    from paper_2404_01249_amd import Pair, fa, synth
+    t0 = time.perf_counter()
+    mp = synth.microscopy_pair((512, 512, 512), seed=5)
+    gen_s = time.perf_counter() - t0
+    scales, iters = [8.0, 4.0, 2.0, 1.0], [200, 200, 100, 50]
+    vox = sum(int(np.prod([max(1, int(np.floor(512 / s + 0.5)))] * 3)) * it for s, it in zip(scales, iters))
+    fixed = torch.from_numpy(mp.fixed).cuda()
+    moving = torch.from_numpy(mp.moving).cuda()
+    del mp
+    stream = torch.cuda.current_stream()
+    kw = dict(params)
+    kw["window"] = 7
+    pr = Pair(fixed, moving, stream=stream, **kw)
+    pr.set_schedule(scales, iters)
+    pr.run()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        pr.set_schedule(scales, iters)
+        pr.run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    loss = pr.loss_history()
+    # the same with launch shapes tuned on this GPU (kept for the process until cleared)
+    pr.set_schedule(scales, iters)
+    pr.autotune(trials=5)
+    pr.run()
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        pr.set_schedule(scales, iters)
+        pr.run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    tuned_ms = start.elapsed_time(end) / steps
+    fa.fa_autotune_clear()
+    fa.fa_pair_profile(pr.handle, True)
+    pr.set_schedule(scales, iters)
+    pr.run()
+    split = {}
+    for lvl in range(len(scales)):
+        row = {}
+        for kind, name in enumerate(("grad_adam", "smooth_max", "compose", "smooth_warp")):
+            tot, n = fa.fa_pair_get_profile(pr.handle, lvl, kind)
+            row[name] = round(tot / max(n, 1) * 1e3, 1)
+        split[f"level{lvl}"] = row
+    fa.fa_pair_profile(pr.handle, False)
+    pr.close()
+    return ms, vox, float(loss[0]), float(loss[-1]), gen_s, split, tuned_ms
 
 
 def run_symmetric(p, steps, params):
@@ -442,6 +507,8 @@ def main():
                     help="grid-search batch: skip the sequential comparison (for kernel traces)")
     ap.add_argument("--inverse-steps", type=int, default=2,
                     help="timed fits of the post hoc inverse of the result (0 skips)")
+    ap.add_argument("--large-steps", type=int, default=1,
+                    help="timed registrations of the 512^3 microscopy-like workload (0 skips)")
     ap.add_argument("--tune-steps", type=int, default=2,
                     help="timed registrations with autotuned launch shapes (0 skips)")
     ap.add_argument("--sym-steps", type=int, default=2,
@@ -550,6 +617,14 @@ def main():
                           "schedule": "scales [4.0, 2.0, 1.0] at [100, 50, 25], eta 0.2",
                           "cost_first": float(iloss[0]), "cost_final": float(iloss[-1]),
                           "rms_residual_final": float(np.sqrt(iloss[-1] / 2.0))}
+    if args.large_steps > 0:
+        lms, lvox, l0, l1, gen_s, lsplit, ltuned = run_microscopy512(args.large_steps, params)
+        out["microscopy512"] = {
+            "workload": "512x512x512 microscopy-like pair (seed 5), LNCC 7^3, scales [8, 4, 2, 1] at "
+                        "[200, 200, 100, 50] iterations, eta 0.5, sigma_grad 1.0, sigma_warp 0.5",
+            "ms_per_step": lms, "voxel_iters": lvox, "voxel_iters_per_s": lvox / (lms * 1e-3),
+            "loss_first": l0, "loss_final": l1, "generation_s": gen_s, "kernel_us_by_level": lsplit,
+            "autotuned_ms_per_step": ltuned, "autotuned_speedup": lms / ltuned}
     if args.tune_steps > 0:
         tms, tune_s, tloss, shapes = run_autotuned(p, args.tune_steps, params)
         out["autotuned"] = {"ms_per_step": tms, "speedup": ms / tms, "tuning_s": tune_s, "final_loss": tloss,
