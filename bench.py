@@ -25,6 +25,9 @@ Prints one JSON line.  Besides the headline value it reports
 * ``inverse``: the post hoc inverse of the result (psi = phi^{-1} fitted by
   the same loop on the inverse-consistency cost): time per fit and the final
   cost;
+* ``lncc128``: the fused LNCC cost and gradient (the differentiable loss of
+  fa_lncc.h) against PyTorch autograd of grid_sample + conv3d LNCC, 128^3,
+  windows 5^3 and 9^3;
 * ``microscopy512``: the 512^3 microscopy-like workload (LNCC 7^3, four
   levels): time per registration and the per-level kernel split;
 * ``autotuned``: the same registration with launch shapes picked on this GPU
@@ -223,6 +226,69 @@ def run_autotuned(p, steps, params):
     pr.close()
     fa.fa_autotune_clear()
     return start.elapsed_time(end) / steps, tune_s, float(loss[-1]), shapes
+
+
+def run_lncc128(reps=20):
+    """The fused LNCC cost and gradient (fa_lncc.h) on the 128^3 gradient-check
+    pair at a seeded smooth displacement (max 2 voxels), windows 5^3 and 9^3,
+    against the same cost written with PyTorch operators (grid_sample warp,
+    conv3d window sums) and differentiated by autograd.  Per window:
+    milliseconds per forward + backward for the fused autograd Function, for
+    the single fused pass (loss_and_grad) and for PyTorch autograd (HIP
+    events, mean of `reps` after a warm-up), and the relative L2 difference of
+    the two gradients."""
+    import torch
+
+    import bench_plain
+    from paper_2404_01249_amd import LNCC, synth
+    p = synth.load("blobs128")
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    d0 = torch.from_numpy(synth.smooth_field(p.fixed.shape, 31, sigma=6.0, max_norm=2.0)).cuda()
+    stream = torch.cuda.current_stream()
+    shape = tuple(p.fixed.shape)
+    ident = torch.stack(torch.meshgrid(*[torch.arange(n, device="cuda", dtype=torch.float32) for n in shape],
+                                       indexing="ij"))[None]
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(reps):
+            r = fn()
+        end.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / reps, r
+
+    for w in (5, 9):
+        lncc = LNCC(shape, window=w)
+        n = bench_plain.box(torch.ones((1, 1) + shape, device="cuda"), w)
+        If, Im = fixed[None, None], moving[None, None]
+
+        def fused_autograd():
+            d = d0.clone().requires_grad_(True)
+            lncc(fixed, moving, d).backward()
+            return d.grad
+
+        def fused_pass():
+            return lncc.loss_and_grad(fixed, moving, d0)[1]
+
+        def torch_autograd():
+            d = d0[None].clone().requires_grad_(True)
+            J = bench_plain.warp(Im, ident + d)
+            bench_plain.lncc_loss(If, J, w, 1e-5, n).backward()
+            return d.grad[0]
+
+        ms_f, g_f = timed(fused_autograd)
+        ms_p, _ = timed(fused_pass)
+        ms_t, g_t = timed(torch_autograd)
+        rel = float((g_f - g_t).norm() / g_t.norm())
+        out[f"window{w}"] = {"fused_autograd_ms": ms_f, "fused_single_pass_ms": ms_p, "torch_autograd_ms": ms_t,
+                             "speedup_autograd": ms_t / ms_f, "grad_rel_l2_vs_torch": rel}
+        lncc.close()
+    return out
 
 
 def run_microscopy512(steps, params):
@@ -507,6 +573,7 @@ def main():
                     help="grid-search batch: skip the sequential comparison (for kernel traces)")
     ap.add_argument("--inverse-steps", type=int, default=2,
                     help="timed fits of the post hoc inverse of the result (0 skips)")
+    ap.add_argument("--no-lncc", action="store_true", help="skip the fused LNCC vs autograd timing (128^3)")
     ap.add_argument("--large-steps", type=int, default=1,
                     help="timed registrations of the 512^3 microscopy-like workload (0 skips)")
     ap.add_argument("--tune-steps", type=int, default=2,
@@ -617,6 +684,8 @@ def main():
                           "schedule": "scales [4.0, 2.0, 1.0] at [100, 50, 25], eta 0.2",
                           "cost_first": float(iloss[0]), "cost_final": float(iloss[-1]),
                           "rms_residual_final": float(np.sqrt(iloss[-1] / 2.0))}
+    if not args.no_lncc:
+        out["lncc128"] = run_lncc128()
     if args.large_steps > 0:
         lms, lvox, l0, l1, gen_s, lsplit, ltuned = run_microscopy512(args.large_steps, params)
         out["microscopy512"] = {
