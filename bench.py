@@ -654,6 +654,11 @@ def main():
         import torch
         zero = torch.zeros_like(field)
         out["accuracy"] = {"fused": acc, "identity_dice": accuracy(p, zero)["dice"]}
+        if p.true_field is not None:
+            from paper_2404_01249_amd import evaluate
+            g = torch.from_numpy(p.true_field).cuda()
+            out["accuracy"]["endpoint_error_vs_true_warp"] = {
+                "fused": evaluate.endpoint_error(field, g)[0], "identity": evaluate.endpoint_error(zero, g)[0]}
     if args.batch > 0:
         bt = run_batch_compare(p, min(args.batch, 8), params)
         nb = min(args.batch, 8)
@@ -717,6 +722,13 @@ def main():
                 pacc = accuracy(p, pfield)
                 out["accuracy"]["plain_torch"] = pacc
                 out["accuracy"]["dice_difference"] = acc["dice"] - pacc["dice"]
+                if "endpoint_error_vs_true_warp" in out["accuracy"]:
+                    import torch
+
+                    from paper_2404_01249_amd import evaluate
+                    g = torch.from_numpy(p.true_field).cuda()
+                    out["accuracy"]["endpoint_error_vs_true_warp"]["plain_torch"] = \
+                        evaluate.endpoint_error(pfield.contiguous(), g)[0]
         except Exception as e:  # the comparison must not hide the headline line
             out["plain_torch"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:

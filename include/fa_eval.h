@@ -56,6 +56,16 @@ fa_status fa_label_overlap(const int8_t* a_dev, const int8_t* b_dev, int64_t n, 
 fa_status fa_jacobian_det(const float* d_dev, fa_shape shape, double* det_dev, int64_t* n_nonpos_host,
                           int64_t* n_interior_host, void* hip_stream);
 
+/* out = u + d(x + u): the displacement of (id + d) o (id + u), with d sampled
+ * trilinearly per component and zero outside the grid (the composition of
+ * Algorithm 1's retraction).  With u a registration's result and d the warp
+ * that made the moving image from the fixed one (moving(x) = fixed(x + d(x))),
+ * out is the registration's residual: zero where it recovered that warp
+ * exactly.  u, d, out: device float32 [3][n0][n1][n2]; out must not alias d.
+ * Enqueued.  FA_EINVAL (NULL pointer), FA_ESHAPE. */
+fa_status fa_compose_fields(const float* u_dev, const float* d_dev, fa_shape shape, float* out_dev,
+                            void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

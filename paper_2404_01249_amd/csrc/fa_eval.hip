@@ -227,4 +227,13 @@ fa_status fa_jacobian_det(const float* d_dev, fa_shape shape, double* det_dev, i
   return FA_OK;
 }
 
+fa_status fa_compose_fields(const float* u_dev, const float* d_dev, fa_shape shape, float* out_dev,
+                            void* hip_stream) {
+  if (!u_dev || !d_dev || !out_dev) return fail(FA_EINVAL, "u, d and out must not be NULL");
+  if (out_dev == d_dev) return fail(FA_EINVAL, "out must not alias d");
+  FA_TRY(fa::check_shape(shape));
+  FA_HIP(fa::launch_compose_fields(u_dev, d_dev, out_dev, shape.n0, shape.n1, shape.n2, (hipStream_t)hip_stream));
+  return FA_OK;
+}
+
 }  // extern "C"

@@ -50,3 +50,20 @@ def singular_fraction(d) -> float:
     """Fraction of interior voxels with det(I + grad d) <= 0."""
     nonpos, interior = fa.fa_jacobian_det(d, None, count=True)
     return nonpos / interior if interior else float("nan")
+
+
+def compose(u, d):
+    """u + d(x + u) (fa_compose_fields): the displacement of (id + d) o (id + u)."""
+    out = torch.empty_like(u)
+    fa.fa_compose_fields(u.contiguous(), d.contiguous(), out)
+    return out
+
+
+def endpoint_error(d_reg, g_true, margin=8):
+    """Mean and max of |d_reg(x) + g_true(x + d_reg(x))| over voxels at least
+    `margin` from every face: the distance by which a registration result
+    misses the warp that made the moving image (moving(x) = fixed(x + g(x)))."""
+    r = compose(d_reg, g_true)
+    core = (slice(None),) + tuple(slice(margin, n - margin) for n in r.shape[1:])
+    e = r[core].norm(dim=0)
+    return float(e.mean()), float(e.max())

@@ -95,6 +95,7 @@ SIGNATURES = {
     "fa_warp_labels": (_I, [_P, _P, fa_shape, _P, _P]),
     "fa_label_overlap": (_I, [_P, _P, _I64, _I, _I64P, _P]),
     "fa_jacobian_det": (_I, [_P, fa_shape, _P, _I64P, _I64P, _P]),
+    "fa_compose_fields": (_I, [_P, _P, fa_shape, _P, _P]),
 }
 
 _lib = None
@@ -463,3 +464,10 @@ def fa_batch_step_fused(pairs, max_iters: int) -> int:
     fin = ctypes.c_int(0)
     _check(load_library().fa_batch_step_fused(arr, len(pairs), int(max_iters), ctypes.byref(fin)))
     return fin.value
+
+
+def fa_compose_fields(u, d, out, stream=None):
+    if u.shape != d.shape or u.shape != out.shape or u.dim() != 4 or u.shape[0] != 3:
+        raise ValueError("u, d and out must be (3, n0, n1, n2) fields of one shape")
+    shape = fa_shape(*[int(s) for s in u.shape[1:]])
+    _check(load_library().fa_compose_fields(_ptr(u), _ptr(d), shape, _ptr(out), _stream_handle(stream)))

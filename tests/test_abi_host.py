@@ -173,3 +173,11 @@ def test_symmetric_rejects_bad_arguments_before_any_device_work(lib):
 def test_autotune_rejects_bad_arguments(lib):
     assert lib.fa_pair_autotune(None, 5) == fa.FA_EINVAL
     assert lib.fa_pair_get_tiling(None, 0, 0, None, None, None, None) == fa.FA_EINVAL
+
+
+def test_compose_fields_rejects_bad_arguments(lib):
+    shp = fa.fa_shape(4, 5, 6)
+    p = ctypes.c_void_p
+    assert lib.fa_compose_fields(None, p(32), shp, p(64), None) == fa.FA_EINVAL
+    assert lib.fa_compose_fields(p(16), p(32), shp, p(32), None) == fa.FA_EINVAL   # out aliases d
+    assert lib.fa_compose_fields(p(16), p(32), fa.fa_shape(1, 5, 6), p(64), None) == fa.FA_ESHAPE

@@ -89,6 +89,23 @@ def test_jacobian_det_without_interior():
     assert np.isnan(evaluate.singular_fraction(dev(d)))
 
 
+@pytest.mark.parametrize("shape", [(21, 37, 45), (7, 5, 6)])
+def test_compose_fields_matches_oracle(shape):
+    """u + d(x + u) against the oracle's composition (fp64), with samples off
+    the grid near the faces."""
+    u = synth.smooth_field(shape, 61, sigma=2.0, max_norm=3.0)
+    d = synth.smooth_field(shape, 62, sigma=2.0, max_norm=2.0)
+    got = host(evaluate.compose(dev(u), dev(d))).astype(np.float64)
+    ref = O.compose(d.astype(np.float64), u.astype(np.float64))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"{shape}: compose max rel {err:.2e}")
+    assert err <= 1e-6
+    # composing with a zero field is exact
+    z = np.zeros_like(u)
+    assert np.array_equal(host(evaluate.compose(dev(u), dev(z))), u)
+    assert np.array_equal(host(evaluate.compose(dev(z), dev(d))), d)
+
+
 def test_tissue160_registration_matches_stored_oracle_run():
     """The whole 160x192x224 schedule (4x, 2x, 1x at 200/100/50) against the
     oracle's run stored by tests/golden/make_golden.py."""
@@ -111,8 +128,14 @@ def test_tissue160_registration_matches_stored_oracle_run():
     print(f"tissue160: endpoint diff {epe:.4f} vox, loss rel first {rel[0]:.2e} max {rel.max():.2e}, "
           f"Dice {dsc:.4f} (oracle {float(z['dice']):.4f}, identity {float(z['dice_identity']):.4f}), "
           f"singular {sing:.2e}", flush=True)
+    # the distance by which the result misses the warp that made the moving image
+    miss, miss_max = evaluate.endpoint_error(d, dev(p.true_field))
+    miss_id, _ = evaluate.endpoint_error(torch.zeros_like(d), dev(p.true_field))
+    print(f"tissue160: endpoint error against the true warp {miss:.3f} vox (max {miss_max:.2f}); "
+          f"identity {miss_id:.3f}", flush=True)
     assert epe <= 0.05
     assert rel[0] <= 1e-5 and rel.max() <= 1e-2
     assert abs(dsc - float(z["dice"])) <= 0.005
     assert sing == float(z["singular"]) == 0.0
+    assert miss < 0.5 * miss_id
     pr.close()
