@@ -1,9 +1,18 @@
 """MI355X-native FireANTs dense matching step (arXiv 2404.01249).
 
 The computation lives in the HIP library ``libfa_mi355x.so`` (C ABI in
-``include/fa.h``); :mod:`paper_2404_01249_amd.fa` binds it with the same
-names, and :class:`Pair` is a convenience wrapper over those calls.  PyTorch
-only provides device memory and streams.
+``include/*.h``); :mod:`paper_2404_01249_amd.fa` binds it with the same
+names.  Convenience wrappers over those calls:
+
+* :class:`Pair` -- one registration (Algorithm 1), with ``autotune``;
+* :func:`run_batch` -- several registrations advanced together (separate
+  streams, or batched launches with optional graph replay);
+* :class:`LNCC` -- the fused cost and gradient as a differentiable loss;
+* :class:`Inverse` -- the post hoc inverse of a warp;
+* :class:`Symmetric` -- the symmetric registration phi_M o phi_F^{-1};
+* :mod:`evaluate` -- label transfer, Dice, det J, field composition.
+
+PyTorch only provides device memory and streams.
 """
 from __future__ import annotations
 
