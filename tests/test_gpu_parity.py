@@ -474,3 +474,51 @@ def _autotune_checks(fixed, moving, ref_loss, ref_d):
     u.set_schedule([2.0, 1.0], [1, 1])
     assert [[u.tiling(level, kind) for kind in range(4)] for level in (0, 1)] == auto
     u.close()
+
+
+def random_configs(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        shape = tuple(int(v) for v in rng.integers(6, 40, 3))
+        out.append(dict(shape=shape, window=int(rng.choice([1, 3, 5, 7, 9])),
+                        sigma_grad=float(rng.choice([0.0, 0.5, 1.0, 1.5])),
+                        sigma_warp=float(rng.choice([0.0, 0.5, 1.0])),
+                        eta=float(rng.choice([0.25, 1.0, 3.0])), use_jac=bool(rng.integers(0, 2)),
+                        seed=int(rng.integers(0, 10000))))
+    return out
+
+
+@pytest.mark.parametrize("cfg", random_configs(12, 2024), ids=lambda c: "x".join(map(str, c["shape"])) +
+                         f"-w{c['window']}-g{c['sigma_grad']}-s{c['sigma_warp']}-e{c['eta']}-j{int(c['use_jac'])}")
+def test_random_configurations_match_oracle(cfg):
+    """Seeded random shapes, windows, Gaussian widths, step sizes (eta = 3
+    takes the composition with gathers) and use_jac: a two-level run of 3 + 2
+    iterations against the oracle (loss history and final field)."""
+    fixed, moving, _ = make_problem(cfg["shape"], seed=cfg["seed"])
+    kw = {k: cfg[k] for k in ("window", "sigma_grad", "sigma_warp", "eta", "use_jac")}
+    scales, iters = [2.0, 1.0], [3, 2]
+    if min(cfg["shape"]) < 8:
+        scales, iters = [1.0], [4]
+    pr = new_pair(fixed, moving, **kw)
+    pr.set_schedule(scales, iters)
+    assert pr.run() == sum(iters)
+    loss = pr.loss_history().astype(np.float64)
+    d = host(pr.field())
+    pr.close()
+    P = O.Params(eta=cfg["eta"], sigma_grad=cfg["sigma_grad"], sigma_warp=cfg["sigma_warp"], window=cfg["window"],
+                 use_jac=cfg["use_jac"])
+    d_ref, loss_ref, _ = O.register(fixed, moving, scales, iters, P)
+    rel = np.abs(loss - np.asarray(loss_ref)) / np.maximum(np.abs(loss_ref), 1e-12)
+    epe = np.sqrt(((d - d_ref) ** 2).sum(0))
+    q = float(np.quantile(epe, 0.999))
+    print(f"{cfg}: loss rel max {rel.max():.2e}, endpoint diff mean {epe.mean():.2e} "
+          f"99.9% {q:.2e} max {epe.max():.2e}")
+    assert rel[0] <= 1e-5 and rel.max() <= 1e-3
+    # The position derivative jumps where a sample crosses a cell boundary
+    # (the cell is the floor of the position).  A sample within fp32 rounding
+    # of an integer can take the other cell than in the oracle's fp64 state,
+    # and Adam's per-voxel normalisation turns that into a full-size step
+    # difference at that voxel: large steps (eta = 3) with no warp smoothing
+    # show it at a voxel or two.  The mean and nearly every voxel stay close.
+    assert epe.mean() <= 1e-3 and q <= 0.05
