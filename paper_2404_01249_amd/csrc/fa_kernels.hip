@@ -146,6 +146,49 @@ __device__ __forceinline__ float clipped_count(int i, int n, int r) {
   return (float)(min(i + r, n - 1) - max(i - r, 0) + 1);
 }
 
+// Box sums of two neighbouring outputs along a row: out[0] = in[0] + ... +
+// in[W-1] and out[1] = in[1] + ... + in[W], each added left to right as a
+// single output would be.  W is odd and in and out are 8-byte aligned, so the
+// W + 1 inputs arrive as (W + 1) / 2 pair reads and the outputs as one pair
+// write.
+template <int W>
+__device__ __forceinline__ void box_pair_x(const float* in, float* out) {
+  float v[W + 1];
+#pragma unroll
+  for (int k = 0; k < (W + 1) / 2; ++k) {
+    const float2 t = reinterpret_cast<const float2*>(in)[k];
+    v[2 * k] = t.x;
+    v[2 * k + 1] = t.y;
+  }
+  float a = v[0], b = v[1];
+#pragma unroll
+  for (int k = 1; k < W; ++k) {
+    a += v[k];
+    b += v[k + 1];
+  }
+  reinterpret_cast<float2*>(out)[0] = make_float2(a, b);
+}
+
+// The same with tap weights w[0..L-1]: out[0] = sum_k w[k] in[k] and out[1]
+// = sum_k w[k] in[k + 1], each accumulated from k = 0 upwards.
+template <int L>
+__device__ __forceinline__ void tap_pair_x(const float* in, float* out, const float* w) {
+  float v[L + 1];
+#pragma unroll
+  for (int k = 0; k < (L + 1) / 2; ++k) {
+    const float2 t = reinterpret_cast<const float2*>(in)[k];
+    v[2 * k] = t.x;
+    v[2 * k + 1] = t.y;
+  }
+  float a = w[0] * v[0], b = w[0] * v[1];
+#pragma unroll
+  for (int k = 1; k < L; ++k) {
+    a += w[k] * v[k];
+    b += w[k] * v[k + 1];
+  }
+  reinterpret_cast<float2*>(out)[0] = make_float2(a, b);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumber them so that every XCD works through a contiguous range of
 // tiles: neighbouring tiles then share their halo reads in one L2.
@@ -211,6 +254,10 @@ __device__ float block_max(float v, float* red) {
 // corners when the values are consumed.
 __device__ __forceinline__ float load_at(const float* __restrict__ base, unsigned byte_off) {
   return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (size_t)byte_off);
+}
+
+__device__ __forceinline__ void store_at(float* __restrict__ base, unsigned byte_off, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (size_t)byte_off) = v;
 }
 
 __device__ __forceinline__ void axis_offsets(int x, float dd, int n, int stride_bytes, unsigned& lo,
@@ -393,9 +440,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   constexpr int XS1 = E1Y * E2X;
   constexpr int XS2 = E2Y * TX;
   constexpr int CPT1 = 1 + (E1 - NT + NT - 1) / NT;   // own column + halo columns
-  extern __shared__ float lds[];
-  float* buf = lds;             // [5][E1], later [3][E2]
-  float* bufx = lds + 5 * E1;   // [5][XS1], later [3][XS2]
+  // The in-plane x passes give each thread two neighbouring outputs (pair
+  // reads along rows): every row length and array offset below is even.
+  static_assert(TX % 2 == 0 && W % 2 == 1, "pairs need an even tile width and an odd window");
+  extern __shared__ __attribute__((aligned(16))) float glds[];
+  float* buf = glds;             // [5][E1], later [3][E2]
+  float* bufx = glds + 5 * E1;   // [5][XS1], later [3][XS2]
   // grad_p I_m of the own column, delayed 2r planes from the input plane
   // to the output plane: a per-thread delay line of GS slots in LDS (slot
   // z mod GS).  Each thread touches only its own entries, so no barrier is
@@ -404,7 +454,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   constexpr int GS = (R == 0) ? 1 : 2 * R;
   // in LDS while the kernel's LDS stays within 64 KiB, else in registers
   constexpr bool GLDS = sizeof(float) * (5 * E1 + 5 * XS1 + 3 * GS * NT) <= 65536;
-  float* gring = lds + 5 * E1 + 5 * XS1;   // [GS][3][NT] when GLDS
+  float* gring = glds + 5 * E1 + 5 * XS1;   // [GS][3][NT] when GLDS
   float greg[3][GS];                       // when !GLDS: oldest entry first
 #pragma unroll
   for (int j = 0; j < GS; ++j) greg[0][j] = greg[1][j] = greg[2][j] = 0.0f;
@@ -500,11 +550,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
 
   auto load_raw = [&](int z, int k) {
     if (z >= 0 && z < n0 && cin[k]) {
-      const int idx = vidx(z, cy[k], cx[k], n1, n2);
-      nd0[k] = A.d[idx];
-      nd1[k] = A.d[N + idx];
-      nd2[k] = A.d[2 * N + idx];
-      nf[k] = A.fixed[idx];
+      // byte offsets from uniform bases (volumes hold < 2^29 voxels)
+      const unsigned off = (unsigned)vidx(z, cy[k], cx[k], n1, n2) * 4u;
+      nd0[k] = load_at(A.d, off);
+      nd1[k] = load_at(A.d + N, off);
+      nd2[k] = load_at(A.d + 2 * N, off);
+      nf[k] = load_at(A.fixed, off);
     }
   };
   auto issue_gather = [&](int z, int k) {
@@ -589,23 +640,17 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
         }
       }
       __syncthreads();
-      for (int c = tid; c < XS1; c += NT) {
-        const int yy = c / E2X, xo = c - yy * E2X;
-        const float* src = buf + yy * E1X + xo;
-        float s0 = src[0], s1 = src[E1], s2 = src[2 * E1], s3 = src[3 * E1], s4 = src[4 * E1];
-#pragma unroll
-        for (int k = 1; k < W; ++k) {
-          s0 += src[k];
-          s1 += src[E1 + k];
-          s2 += src[2 * E1 + k];
-          s3 += src[3 * E1 + k];
-          s4 += src[4 * E1 + k];
+      {
+        // one quantity at a time: the pair reads of all five at once would
+        // not fit the kernel's register budget
+        constexpr int HX = E2X / 2, PX = E1Y * HX;
+        for (int p = tid; p < PX; p += NT) {
+          const int yy = p / HX, xo = 2 * (p - yy * HX);
+          const float* src = buf + yy * E1X + xo;
+          float* dst = bufx + yy * E2X + xo;
+#pragma unroll 1
+          for (int q = 0; q < 5; ++q) box_pair_x<W>(src + q * E1, dst + q * XS1);
         }
-        bufx[c] = s0;
-        bufx[XS1 + c] = s1;
-        bufx[2 * XS1 + c] = s2;
-        bufx[3 * XS1 + c] = s3;
-        bufx[4 * XS1 + c] = s4;
       }
       __syncthreads();
       const int zc1 = zin - R;
@@ -651,19 +696,15 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
         buf[2 * E2 + c] = cc_;
       }
       __syncthreads();
-      for (int c = tid; c < XS2; c += NT) {
-        const int yy = c / TX, xo = c - yy * TX;
-        const float* src = buf + yy * E2X + xo;
-        float s0 = src[0], s1 = src[E2], s2 = src[2 * E2];
+      {
+        constexpr int HX = TX / 2, PX = E2Y * HX;
+        for (int p = tid; p < PX; p += NT) {
+          const int yy = p / HX, xo = 2 * (p - yy * HX);
+          const float* src = buf + yy * E2X + xo;
+          float* dst = bufx + yy * TX + xo;
 #pragma unroll
-        for (int k = 1; k < W; ++k) {
-          s0 += src[k];
-          s1 += src[E2 + k];
-          s2 += src[2 * E2 + k];
+          for (int q = 0; q < 3; ++q) box_pair_x<W>(src + q * E2, dst + q * XS2);
         }
-        bufx[c] = s0;
-        bufx[XS2 + c] = s1;
-        bufx[2 * XS2 + c] = s2;
       }
       __syncthreads();
       {
@@ -687,12 +728,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
       }
       const int zc2 = zc1 - R;
       if (zc2 >= z0 && out_col) {
-        const int idx = vidx(zc2, gy, gx, n1, n2);
+        const unsigned off = (unsigned)vidx(zc2, gy, gx, n1, n2) * 4u;
         if (A.mode == 0 && !mv_ready) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            pm[q] = A.m[q * N + idx];
-            pv[q] = A.v[q * N + idx];
+            pm[q] = load_at(A.m + q * N, off);
+            pv[q] = load_at(A.v + q * N, off);
           }
         }
         float SA = ringA[0], SB = ringB[0], SC = ringC[0];
@@ -719,25 +760,25 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
           const float b1 = A.beta1, b2 = A.beta2;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            const int iq = q * N + idx;
             const float mm = b1 * pm[q] + (1.0f - b1) * g[q];
             const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
-            A.m[iq] = mm;
-            A.v[iq] = vv;
-            A.out[iq] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps);
+            store_at(A.m + q * N, off, mm);
+            store_at(A.v + q * N, off, vv);
+            store_at(A.out + q * N, off, (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps));
           }
           // Adam moments of the next output plane
           mv_ready = zc2 + 1 < z1;
           if (mv_ready) {
+            const unsigned noff = off + (unsigned)(n1 * n2) * 4u;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-              pm[q] = A.m[q * N + idx + n1 * n2];
-              pv[q] = A.v[q * N + idx + n1 * n2];
+              pm[q] = load_at(A.m + q * N, noff);
+              pv[q] = load_at(A.v + q * N, noff);
             }
           }
         } else if (A.mode == 1) {
 #pragma unroll
-          for (int q = 0; q < 3; ++q) A.out[q * N + idx] = g[q] * gsc;
+          for (int q = 0; q < 3; ++q) store_at(A.out + q * N, off, g[q] * gsc);
         }
       }
     }
@@ -816,10 +857,13 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   constexpr int CPT = (E + NT - 1) / NT;
   constexpr int DY = TY + 2, DX = TX + 2, DE = DY * DX;  // staged d planes (EPI_COMPOSE_LDS)
   constexpr int CPTD = (DE + NT - 1) / NT;
-  extern __shared__ float lds[];
-  float* buf = lds;           // [3][E]
-  float* bufx = lds + 3 * E;  // [3][XS]
-  float* dring = lds + 3 * E + 3 * XS;  // [3 planes][3][DE] (EPI_COMPOSE_LDS)
+  // the x pass gives each thread two neighbouring outputs (pair reads along
+  // rows): EX, E, XS and every row offset are even
+  static_assert(TX % 2 == 0, "pairs need an even tile width");
+  extern __shared__ __attribute__((aligned(16))) float glds[];
+  float* buf = glds;           // [3][E]
+  float* bufx = glds + 3 * E;  // [3][XS]
+  float* dring = glds + 3 * E + 3 * XS;  // [3 planes][3][DE] (EPI_COMPOSE_LDS)
   __shared__ double red[NT / 64];
   __shared__ int is_last;
 
@@ -871,10 +915,11 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       if (cuse[k]) {
-        const int idx = base + coff[k];
-        pre[k][0] = A.in[idx];
-        pre[k][1] = A.in[N + idx];
-        pre[k][2] = A.in[2 * N + idx];
+        // byte offsets from uniform bases (volumes hold < 2^29 voxels)
+        const unsigned off = (unsigned)(base + coff[k]) * 4u;
+        pre[k][0] = load_at(A.in, off);
+        pre[k][1] = load_at(A.in + N, off);
+        pre[k][2] = load_at(A.in + 2 * N, off);
       }
     }
   };
@@ -889,10 +934,10 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
       const int c = tid + k * NT;
       const int yy = y0 - 1 + c / DX, xx = x0 - 1 + c % DX;
       const bool ok = c < DE && pz >= 0 && pz < n0 && yy >= 0 && yy < n1 && xx >= 0 && xx < n2;
-      const int idx = ok ? (pz * n1 + yy) * n2 + xx : 0;
-      pd[k][0] = ok ? A.d[idx] : 0.0f;
-      pd[k][1] = ok ? A.d[N + idx] : 0.0f;
-      pd[k][2] = ok ? A.d[2 * N + idx] : 0.0f;
+      const unsigned off = ok ? (unsigned)((pz * n1 + yy) * n2 + xx) * 4u : 0u;
+      pd[k][0] = ok ? load_at(A.d, off) : 0.0f;
+      pd[k][1] = ok ? load_at(A.d + N, off) : 0.0f;
+      pd[k][2] = ok ? load_at(A.d + 2 * N, off) : 0.0f;
     }
   };
   auto store_dplane = [&](int pz) {
@@ -962,19 +1007,15 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
       store_dplane(zin - R + 1);
       if (zin + 1 < z1 + R) load_dplane(zin - R + 2);
     }
-    for (int c = tid; c < XS; c += NT) {
-      const int yy = c / TX, xo = c - yy * TX;
-      const float* src = buf + yy * EX + xo;
-      float s0 = w[0] * src[0], s1 = w[0] * src[E], s2 = w[0] * src[2 * E];
+    {
+      constexpr int HX = TX / 2, PX = EY * HX;
+      for (int p = tid; p < PX; p += NT) {
+        const int yy = p / HX, xo = 2 * (p - yy * HX);
+        const float* src = buf + yy * EX + xo;
+        float* dst = bufx + yy * TX + xo;
 #pragma unroll
-      for (int k = 1; k < L; ++k) {
-        s0 += w[k] * src[k];
-        s1 += w[k] * src[E + k];
-        s2 += w[k] * src[2 * E + k];
+        for (int q = 0; q < 3; ++q) tap_pair_x<L>(src + q * E, dst + q * XS, w);
       }
-      bufx[c] = s0;
-      bufx[XS + c] = s1;
-      bufx[2 * XS + c] = s2;
     }
     __syncthreads();
     if (EPI == EPI_COMPOSE) finish_compose();
@@ -1008,16 +1049,17 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
         v2 += w[j] * ring[2][j];
       }
       const int idx = vidx(zo, gy, gx, n1, n2);
+      const unsigned off = (unsigned)idx * 4u;
       if (EPI == EPI_STORE || EPI == EPI_STORE_FINAL) {
-        A.out[idx] = v0;
-        A.out[N + idx] = v1;
-        A.out[2 * N + idx] = v2;
+        store_at(A.out, off, v0);
+        store_at(A.out + N, off, v1);
+        store_at(A.out + 2 * N, off, v2);
       } else if (EPI == EPI_MAXNORM) {
         mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
       } else if (EPI == EPI_SMOOTH_MAX) {
-        A.out[idx] = v0;
-        A.out[N + idx] = v1;
-        A.out[2 * N + idx] = v2;
+        store_at(A.out, off, v0);
+        store_at(A.out + N, off, v1);
+        store_at(A.out + 2 * N, off, v2);
         mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
       } else if (EPI == EPI_COMPOSE_LDS) {
         // d' = u + d(x + u) from the staged planes zo - 1 .. zo + 1; the
@@ -1044,9 +1086,9 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
           const float g1 = e10 + t1 * (e11 - e10);
           res[q] = g0 + t0 * (g1 - g0);
         }
-        A.out[idx] = u0 + res[0];
-        A.out[N + idx] = u1 + res[1];
-        A.out[2 * N + idx] = u2 + res[2];
+        store_at(A.out, off, u0 + res[0]);
+        store_at(A.out + N, off, u1 + res[1]);
+        store_at(A.out + 2 * N, off, u2 + res[2]);
       } else {  // EPI_COMPOSE: d' = u + d(x + u); finished next plane step
         cu[0] = scale * v0;
         cu[1] = scale * v1;
