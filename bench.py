@@ -138,6 +138,46 @@ def run_fused(p, steps, warmup, params, prof_steps=2):
     return ms, wall / steps, prof, loss, field
 
 
+def run_steady_graph(p, params, short=10, long=60, reps=5):
+    """Steady-state finest-level time per iteration from HIP-graph replay.
+
+    One pair on a single-level schedule at scale 1 (more iterations than are
+    run) is advanced through fa_batch_step_fused with graph capture on.  Each
+    call runs its first iteration eagerly, captures the next and replays the
+    rest, so a call of `long` iterations and one of `short` differ by
+    long - short replayed iterations; their HIP-event times (on the pair's
+    stream, which the call joins) differ by those alone.  Median over `reps`
+    such differences after one warm-up pair of calls; microseconds."""
+    import statistics
+
+    import torch
+
+    from paper_2404_01249_amd import Pair, run_batch
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    stream = torch.cuda.current_stream()
+    pr = Pair(fixed, moving, stream=stream, **params)
+    pr.set_schedule([1.0], [1 << 20])
+
+    def timed(n):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run_batch([pr], max_iters=n, graphs=True)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    timed(short)
+    timed(long)
+    diffs = []
+    for _ in range(reps):
+        t_short = timed(short)
+        t_long = timed(long)
+        diffs.append((t_long - t_short) / (long - short) * 1e3)
+    pr.close()
+    return statistics.median(diffs)
+
+
 def run_use_jac(p, steps, params):
     """Whole registrations with Algorithm 1's use_jac on (Eulerian descent,
     Section 4.4.2): milliseconds per registration and the final loss."""
@@ -582,6 +622,8 @@ def main():
                     help="timed symmetric registrations (0 skips)")
     ap.add_argument("--jac-steps", type=int, default=2,
                     help="registrations timed with use_jac on (0 skips)")
+    ap.add_argument("--graph-reps", type=int, default=5,
+                    help="repeats of the graph-replayed finest-level steady-state timing (0 skips)")
     ap.add_argument("--prof-steps", type=int, default=2,
                     help="registrations run with per-kernel HIP events after the timed ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -633,7 +675,16 @@ def main():
             split[f"level{lvl}"] = {names[k]: round(rows[k][0] / max(rows[k][1], 1) * 1e3, 2) for k in range(4)}
         iter_ms_fin = sum(r[0] for r in prof[fin]) / g_n
         steady = {"us_per_iteration": iter_ms_fin * 1e3, "voxel_iters_per_s": n_fin / (iter_ms_fin / 1e3),
-                  "roofline_frac_80B": GRAD_BYTES_PER_VOXEL * n_fin / (iter_ms_fin / 1e3) / 1e9 / HBM_PEAK_GBS}
+                  "roofline_frac_80B": GRAD_BYTES_PER_VOXEL * n_fin / (iter_ms_fin / 1e3) / 1e9 / HBM_PEAK_GBS,
+                  "source": "sum of the four kernels' average HIP-event times at the finest level"}
+    if args.graph_reps > 0:
+        g_us = run_steady_graph(p, params, reps=args.graph_reps)
+        steady = dict(steady or {})
+        steady["graph_replay"] = {
+            "us_per_iteration": g_us, "voxel_iters_per_s": n_fin / (g_us / 1e6),
+            "roofline_frac_80B": GRAD_BYTES_PER_VOXEL * n_fin / (g_us / 1e6) / 1e9 / HBM_PEAK_GBS,
+            "method": "one pair at the finest level through fa_batch_step_fused with HIP-graph capture; "
+                      "(60-iteration call - 10-iteration call) / 50, median of %d" % args.graph_reps}
 
     out = {
         "metric": METRIC, "value": value, "unit": "voxel-iters/s", "n_gpus": 1,
