@@ -113,16 +113,18 @@ def run_fused(p, steps, warmup, params, prof_steps=2):
         pr.set_schedule(p.scales, p.iters)
         pr.run()
     torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(steps):
+    marks[0].record(stream)
+    for k in range(steps):
         pr.set_schedule(p.scales, p.iters)
         pr.run()
-    end.record(stream)
+        marks[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end) / steps
+    ms = marks[0].elapsed_time(marks[-1]) / steps
+    per_run = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+    median_ms = per_run[steps // 2] if steps % 2 else 0.5 * (per_run[steps // 2 - 1] + per_run[steps // 2])
     loss = pr.loss_history()
     field = pr.field()
     fa.fa_pair_profile(pr.handle, True)
@@ -135,7 +137,7 @@ def run_fused(p, steps, warmup, params, prof_steps=2):
     fa.fa_pair_profile(pr.handle, False)
     torch.cuda.synchronize()
     pr.close()
-    return ms, wall / steps, prof, loss, field
+    return ms, median_ms, wall / steps, prof, loss, field
 
 
 def run_steady_graph(p, params, short=10, long=60, reps=5):
@@ -655,7 +657,7 @@ def main():
     lv = level_voxels(p.fixed.shape, p.scales, p.iters)
     vox_iters = sum(n * t for n, t in lv)
 
-    ms, wall_ms, prof, loss, field = run_fused(p, args.steps, args.warmup, params, args.prof_steps)
+    ms, median_ms, wall_ms, prof, loss, field = run_fused(p, args.steps, args.warmup, params, args.prof_steps)
     value = vox_iters / (ms / 1e3)
 
     # dominant kernel: the fused gradient kernel at the finest level
@@ -698,6 +700,7 @@ def main():
         "steady_state_finest": steady,
         "kernel_us_by_level": split,
         "wall_ms_per_step": wall_ms * 1e3,
+        "ms_per_step_median": median_ms,
         "final_loss": float(loss[-1]) if len(loss) else None,
     }
     acc = accuracy(p, field)
