@@ -14,6 +14,7 @@
 #include "fa_internal.h"
 #include "fa_inverse.h"
 
+using fa::clamp_med3;
 using fa::Ctl;
 using fa::fail;
 using fa::Tiling;
@@ -47,9 +48,9 @@ __device__ __forceinline__ Cell cell_of(float p0, float p1, float p2, int n0, in
   c.t1 = p1 - f1;
   c.t2 = p2 - f2;
   // far outside, the clamp keeps the integers small; every corner is then off the grid anyway
-  const int i0 = (int)fminf(fmaxf(f0, -2.0f), (float)n0);
-  const int i1 = (int)fminf(fmaxf(f1, -2.0f), (float)n1);
-  const int i2 = (int)fminf(fmaxf(f2, -2.0f), (float)n2);
+  const int i0 = (int)clamp_med3(f0, -2.0f, (float)n0);
+  const int i1 = (int)clamp_med3(f1, -2.0f, (float)n1);
+  const int i2 = (int)clamp_med3(f2, -2.0f, (float)n2);
   c.ok = 0u;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -90,7 +91,7 @@ __device__ __forceinline__ float sample_grad(const float* __restrict__ f, const 
 }
 
 __device__ __forceinline__ unsigned long long to_fixed(float v) {
-  const float vc = fminf(fmaxf(v, -kFixClamp), kFixClamp);
+  const float vc = clamp_med3(v, -kFixClamp, kFixClamp);
   return (unsigned long long)__double2ll_rn((double)vc * kFixScale);
 }
 
@@ -186,9 +187,9 @@ k_inv_splat_lds(const float* __restrict__ d, const float* __restrict__ e, unsign
         t1[k] = c.t1;
         t2[k] = c.t2;
         // the cell's lower corner (clamped as in cell_of: off-grid corners are dropped below)
-        cz[k] = (int)fminf(fmaxf(floorf((float)z + d0), -2.0f), (float)n0);
-        cy[k] = (int)fminf(fmaxf(floorf((float)y + d1), -2.0f), (float)n1);
-        cx[k] = (int)fminf(fmaxf(floorf((float)x + d2), -2.0f), (float)n2);
+        cz[k] = (int)clamp_med3(floorf((float)z + d0), -2.0f, (float)n0);
+        cy[k] = (int)clamp_med3(floorf((float)y + d1), -2.0f, (float)n1);
+        cx[k] = (int)clamp_med3(floorf((float)x + d2), -2.0f, (float)n2);
         lo0 = min(lo0, cz[k]);
         lo1 = min(lo1, cy[k]);
         lo2 = min(lo2, cx[k]);

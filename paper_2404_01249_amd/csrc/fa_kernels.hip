@@ -34,7 +34,7 @@ __device__ __forceinline__ int vidx(int z, int y, int x, int n1, int n2) {
 // (all corners are then off the grid anyway), which also keeps the integer
 // conversion defined.
 __device__ __forceinline__ void cell(float p, int n, int& i, float& t, bool& lo, bool& hi) {
-  p = fminf(fmaxf(p, -2.0f), (float)n + 1.0f);
+  p = clamp_med3(p, -2.0f, (float)n + 1.0f);
   const float f = floorf(p);
   i = (int)f;
   t = p - f;
@@ -54,7 +54,7 @@ __device__ __forceinline__ float ldz(const float* __restrict__ f, int idx, bool 
 // (the trilinear derivative jumps between cells, so the cell matters) and the
 // fraction is exact up to at most half an ulp of 1.
 __device__ __forceinline__ void cell_at(int x, float dd, int n, int& i, float& t, bool& lo, bool& hi) {
-  dd = fminf(fmaxf(dd, (float)(-x - 2)), (float)(n + 1 - x));
+  dd = clamp_med3(dd, (float)(-x - 2), (float)(n + 1 - x));
   const float f = floorf(dd);
   i = x + (int)f;
   t = dd - f;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void store_at(float* __restrict__ base, unsigned byte
 
 __device__ __forceinline__ void axis_offsets(int x, float dd, int n, int stride_bytes, unsigned& lo,
                                              unsigned& hi, bool& lo_ok, bool& hi_ok, float& t) {
-  dd = fminf(fmaxf(dd, (float)(-x - 2)), (float)(n + 1 - x));
+  dd = clamp_med3(dd, (float)(-x - 2), (float)(n + 1 - x));
   const float f = floorf(dd);
   const int i = x + (int)f;
   t = dd - f;
@@ -313,7 +313,7 @@ __device__ __forceinline__ Cell8 cell8_at(int n0, int n1, int n2, int z, int y, 
 // and derivative are 0, as with the masked form.
 __device__ __forceinline__ void axis_offsets_pad(int x, float dd, int n, int stride_bytes, unsigned& lo,
                                                  unsigned& hi, float& t) {
-  dd = fminf(fmaxf(dd, (float)(-x - kPad)), (float)(n - x));
+  dd = clamp_med3(dd, (float)(-x - kPad), (float)(n - x));
   const float f = floorf(dd);
   const int i = x + kPad + (int)f;   // padded index, in [0, n + kPad]
   t = dd - f;
@@ -1066,9 +1066,9 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
         // cell offset floor(u) is -1 or 0 for |u| <= 1 (u = 1 exactly uses
         // offset 0 with fraction 1, which selects the same corner value)
         const float u0 = scale * v0, u1 = scale * v1, u2 = scale * v2;
-        const float f0 = fminf(fmaxf(floorf(u0), -1.0f), 0.0f);
-        const float f1 = fminf(fmaxf(floorf(u1), -1.0f), 0.0f);
-        const float f2 = fminf(fmaxf(floorf(u2), -1.0f), 0.0f);
+        const float f0 = clamp_med3(floorf(u0), -1.0f, 0.0f);
+        const float f1 = clamp_med3(floorf(u1), -1.0f, 0.0f);
+        const float f2 = clamp_med3(floorf(u2), -1.0f, 0.0f);
         const float t0 = u0 - f0, t1 = u1 - f1, t2 = u2 - f2;
         const int sA = (((zo + (int)f0) % 3) + 3) % 3;
         const int sB = (sA + 1) % 3;
@@ -1546,9 +1546,9 @@ __device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int 
   if (own) {
     // the arithmetic of k_gauss<0, EPI_COMPOSE_LDS>: floor(u) is -1 or 0
     const float u0 = scale * sv[0], u1 = scale * sv[1], u2 = scale * sv[2];
-    const float f0 = fminf(fmaxf(floorf(u0), -1.0f), 0.0f);
-    const float f1 = fminf(fmaxf(floorf(u1), -1.0f), 0.0f);
-    const float f2 = fminf(fmaxf(floorf(u2), -1.0f), 0.0f);
+    const float f0 = clamp_med3(floorf(u0), -1.0f, 0.0f);
+    const float f1 = clamp_med3(floorf(u1), -1.0f, 0.0f);
+    const float f2 = clamp_med3(floorf(u2), -1.0f, 0.0f);
     const float t0 = u0 - f0, t1 = u1 - f1, t2 = u2 - f2;
     const int cb = ((tz + 1 + (int)f0) * DY + (ty + 1 + (int)f1)) * DX + (tx + 1 + (int)f2);
     float res[3];
