@@ -1166,19 +1166,21 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
   const int ty = tr / TX, tx = tr - ty * TX;
   const int oz = z0 + tz, oy = y0 + ty, ox = x0 + tx;
   const bool own = oz < n0 && oy < n1 && ox < n2;
-  const int oidx = own ? vidx(oz, oy, ox, n1, n2) : 0;
+  // byte offset of the own voxel from uniform bases (volumes hold < 2^29 voxels)
+  const unsigned ooff = own ? (unsigned)vidx(oz, oy, ox, n1, n2) * 4u : 0u;
   float oI = 0.f, oJ = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   float pm[3] = {0.f, 0.f, 0.f}, pv[3] = {0.f, 0.f, 0.f};
   if (own) {
-    const Cell8 c = cell8_pad(n0, n1, n2, oz, oy, ox, A.d[oidx], A.d[N + oidx], A.d[2 * N + oidx]);
+    const Cell8 c = cell8_pad(n0, n1, n2, oz, oy, ox, load_at(A.d, ooff), load_at(A.d + N, ooff),
+                              load_at(A.d + 2 * N, ooff));
     Gather gq;
     gather_issue(A.moving_pad, c, gq);
-    oI = A.fixed[oidx] - si;
+    oI = load_at(A.fixed, ooff) - si;
     if (A.mode == 0) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        pm[q] = A.m[q * N + oidx];
-        pv[q] = A.v[q * N + oidx];
+        pm[q] = load_at(A.m + q * N, ooff);
+        pv[q] = load_at(A.v + q * N, ooff);
       }
     }
     oJ = gather_value_grad(gq, g0, g1, g2) - sj;
@@ -1191,7 +1193,6 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
   constexpr int KB = 3;                    // batch
 #pragma unroll 1
   for (int k0 = 0; k0 < KQ; k0 += KB) {
-    int qidx[KB];
     bool qok[KB];
     float qd0[KB], qd1[KB], qd2[KB], qf[KB];
 #pragma unroll
@@ -1201,11 +1202,11 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
       const int qy = r / QX, qx = r - qy * QX;
       const int z = z0 - 2 * R + qz, y = y0 - 2 * R + qy, x = x0 - 2 * R + qx;
       qok[j] = k0 + j < KQ && c < NQ && z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2;
-      qidx[j] = qok[j] ? vidx(z, y, x, n1, n2) : 0;
-      qd0[j] = qok[j] ? A.d[qidx[j]] : 0.0f;
-      qd1[j] = qok[j] ? A.d[N + qidx[j]] : 0.0f;
-      qd2[j] = qok[j] ? A.d[2 * N + qidx[j]] : 0.0f;
-      qf[j] = qok[j] ? A.fixed[qidx[j]] : 0.0f;
+      const unsigned off = qok[j] ? (unsigned)vidx(z, y, x, n1, n2) * 4u : 0u;
+      qd0[j] = qok[j] ? load_at(A.d, off) : 0.0f;
+      qd1[j] = qok[j] ? load_at(A.d + N, off) : 0.0f;
+      qd2[j] = qok[j] ? load_at(A.d + 2 * N, off) : 0.0f;
+      qf[j] = qok[j] ? load_at(A.fixed, off) : 0.0f;
     }
     Gather gq[KB];
 #pragma unroll
@@ -1352,17 +1353,16 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
       const float b1 = A.beta1, b2 = A.beta2;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const int iq = q * N + oidx;
         const float mm = b1 * pm[q] + (1.0f - b1) * g[q];
         const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
-        A.m[iq] = mm;
-        A.v[iq] = vv;
-        A.out[iq] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps);
+        store_at(A.m + q * N, ooff, mm);
+        store_at(A.v + q * N, ooff, vv);
+        store_at(A.out + q * N, ooff, (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps));
       }
     } else if (A.mode == 1) {
       const float gsc = A.gscale ? *A.gscale : 1.0f;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) A.out[q * N + oidx] = g[q] * gsc;
+      for (int q = 0; q < 3; ++q) store_at(A.out + q * N, ooff, g[q] * gsc);
     }
   }
   const double tot = block_sum<NT>((double)lacc, red);
@@ -1417,10 +1417,10 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
     const int gz = min(max(z0 - R + zz, 0), n0 - 1);
     const int gy = min(max(y0 - R + yy, 0), n1 - 1);
     const int gx = min(max(x0 - R + xx, 0), n2 - 1);
-    const int idx = (gz * n1 + gy) * n2 + gx;
-    rv[k][0] = A.in[idx];
-    rv[k][1] = A.in[N + idx];
-    rv[k][2] = A.in[2 * N + idx];
+    const unsigned off = (unsigned)((gz * n1 + gy) * n2 + gx) * 4u;
+    rv[k][0] = load_at(A.in, off);
+    rv[k][1] = load_at(A.in + N, off);
+    rv[k][2] = load_at(A.in + 2 * N, off);
   }
 #pragma unroll
   for (int k = 0; k < KR; ++k) {
@@ -1476,10 +1476,10 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
       v1 += w[j] * src[NY + j * TY * TX];
       v2 += w[j] * src[2 * NY + j * TY * TX];
     }
-    const int idx = vidx(gz, gy, gx, n1, n2);
-    A.out[idx] = v0;
-    A.out[N + idx] = v1;
-    A.out[2 * N + idx] = v2;
+    const unsigned off = (unsigned)vidx(gz, gy, gx, n1, n2) * 4u;
+    store_at(A.out, off, v0);
+    store_at(A.out + N, off, v1);
+    store_at(A.out + 2 * N, off, v2);
     if (EPI == EPI_SMOOTH_MAX) mx = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
   }
   if (EPI == EPI_SMOOTH_MAX) {
@@ -1515,10 +1515,10 @@ __device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int 
     const int yy = r / DX, xx = r - yy * DX;
     const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
     const bool ok = c < DE && gz >= 0 && gz < n0 && gy >= 0 && gy < n1 && gx >= 0 && gx < n2;
-    const int idx = ok ? (gz * n1 + gy) * n2 + gx : 0;
-    dv[k][0] = ok ? A.d[idx] : 0.0f;
-    dv[k][1] = ok ? A.d[N + idx] : 0.0f;
-    dv[k][2] = ok ? A.d[2 * N + idx] : 0.0f;
+    const unsigned off = ok ? (unsigned)((gz * n1 + gy) * n2 + gx) * 4u : 0u;
+    dv[k][0] = ok ? load_at(A.d, off) : 0.0f;
+    dv[k][1] = ok ? load_at(A.d + N, off) : 0.0f;
+    dv[k][2] = ok ? load_at(A.d + 2 * N, off) : 0.0f;
   }
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
@@ -1535,12 +1535,12 @@ __device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int 
   const int ty = r / TX, tx = r - ty * TX;
   const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
   const bool own = gz < n0 && gy < n1 && gx < n2;
-  const int idx = own ? vidx(gz, gy, gx, n1, n2) : 0;
+  const unsigned off = own ? (unsigned)vidx(gz, gy, gx, n1, n2) * 4u : 0u;
   float sv[3] = {0.f, 0.f, 0.f};
   if (own) {
-    sv[0] = A.in[idx];
-    sv[1] = A.in[N + idx];
-    sv[2] = A.in[2 * N + idx];
+    sv[0] = load_at(A.in, off);
+    sv[1] = load_at(A.in + N, off);
+    sv[2] = load_at(A.in + 2 * N, off);
   }
   __syncthreads();
   if (own) {
@@ -1564,9 +1564,9 @@ __device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int 
       const float g1 = e10 + t1 * (e11 - e10);
       res[q] = g0 + t0 * (g1 - g0);
     }
-    A.out[idx] = u0 + res[0];
-    A.out[N + idx] = u1 + res[1];
-    A.out[2 * N + idx] = u2 + res[2];
+    store_at(A.out, off, u0 + res[0]);
+    store_at(A.out + N, off, u1 + res[1]);
+    store_at(A.out + 2 * N, off, u2 + res[2]);
   }
 }
 
