@@ -641,8 +641,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
       }
       __syncthreads();
       {
-        // one quantity at a time: the pair reads of all five at once would
-        // not fit the kernel's register budget
+        // one quantity at a time, in a rolled loop (unrolled over the five
+        // quantities the pass measured slower, and it crowds the register
+        // budget)
         constexpr int HX = E2X / 2, PX = E1Y * HX;
         for (int p = tid; p < PX; p += NT) {
           const int yy = p / HX, xo = 2 * (p - yy * HX);
