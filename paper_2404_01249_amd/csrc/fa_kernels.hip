@@ -1804,6 +1804,57 @@ __global__ void k_blur_axis(const float* __restrict__ in, float* __restrict__ ou
   out[i] = s;
 }
 
+// The same blur along n0 or n1 with T consecutive outputs per thread: the
+// T + 2R inputs of a run are loaded once into registers instead of 2R + 1
+// times per output through the caches.  Consecutive threads take consecutive
+// lines (x fastest), so every load is coalesced.  Each output sums the same
+// taps in the same order as k_blur_axis, so the results are bitwise equal.
+template <int R, int T>
+__global__ void __launch_bounds__(256) k_blur_axis_run(const float* __restrict__ in, float* __restrict__ out,
+                                                       int n0, int n1, int n2, int axis,
+                                                       const float* __restrict__ w) {
+  const int n = axis == 0 ? n0 : n1;
+  const int stride = axis == 0 ? n1 * n2 : n2;
+  const int lines = axis == 0 ? n1 * n2 : n0 * n2;
+  const int runs = (n + T - 1) / T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= lines * runs) return;
+  const int l = t % lines, r = t / lines;
+  const int base = axis == 0 ? l : (l / n2) * (n1 * n2) + l % n2;
+  const int p0 = r * T;
+  float wt[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) wt[k] = w[k];
+  float v[T + 2 * R];
+#pragma unroll
+  for (int j = 0; j < T + 2 * R; ++j) v[j] = in[base + min(max(p0 - R + j, 0), n - 1) * stride];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    if (p0 + j < n) {
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * R; ++k) s += wt[k] * v[j + k];
+      out[base + (p0 + j) * stride] = s;
+    }
+  }
+}
+
+// The same blur along n2 on a (n2 / 256, n1, n0) grid: the voxel comes from
+// the block indices, with none of the runtime integer divisions of the flat
+// form, and each lane's 2R + 1 taps are neighbouring floats.  Same taps and
+// order as k_blur_axis (bitwise equal).
+template <int R>
+__global__ void __launch_bounds__(256) k_blur_x(const float* __restrict__ in, float* __restrict__ out, int n2,
+                                                const float* __restrict__ w) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= n2) return;
+  const size_t row = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * (size_t)n2;
+  float s = 0.0f;
+#pragma unroll
+  for (int k = -R; k <= R; ++k) s += w[k + R] * in[row + min(max(x + k, 0), n2 - 1)];
+  out[row + x] = s;
+}
+
 __device__ __forceinline__ float aligned_pos(int i, int nin, int nout) {
   return nout > 1 ? (float)(i * (nin - 1)) / (float)(nout - 1) : 0.0f;
 }
@@ -2251,8 +2302,47 @@ hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int R>
+hipError_t blur_axis_run(const float* in, float* out, int n0, int n1, int n2, int axis, const float* wts,
+                         hipStream_t s) {
+  constexpr int T = 8;
+  const int n = axis == 0 ? n0 : n1;
+  const int64_t threads = (int64_t)n0 * n1 * n2 / n * ((n + T - 1) / T);
+  hipLaunchKernelGGL((k_blur_axis_run<R, T>), dim3(grid1(threads, 256)), dim3(256), 0, s, in, out, n0, n1, n2,
+                     axis, wts);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t blur_x(const float* in, float* out, int n0, int n1, int n2, const float* wts, hipStream_t s) {
+  hipLaunchKernelGGL((k_blur_x<R>), dim3(grid1(n2, 256), n1, n0), dim3(256), 0, s, in, out, n2, wts);
+  return hipGetLastError();
+}
+
 hipError_t launch_blur_axis(const float* in, float* out, int n0, int n1, int n2, int axis,
                             const float* wts, int radius, hipStream_t s) {
+  if (axis == 2 && n0 <= 65535 && n1 <= 65535) {   // grid y and z hold n1 and n0
+    switch (radius) {
+      case 1: return blur_x<1>(in, out, n0, n1, n2, wts, s);
+      case 2: return blur_x<2>(in, out, n0, n1, n2, wts, s);
+      case 3: return blur_x<3>(in, out, n0, n1, n2, wts, s);
+      case 4: return blur_x<4>(in, out, n0, n1, n2, wts, s);
+      case 5: return blur_x<5>(in, out, n0, n1, n2, wts, s);
+      case 6: return blur_x<6>(in, out, n0, n1, n2, wts, s);
+      default: break;
+    }
+  }
+  if (axis != 2) {   // the run form for strided axes (radii of the pyramid's usual scales)
+    switch (radius) {
+      case 1: return blur_axis_run<1>(in, out, n0, n1, n2, axis, wts, s);
+      case 2: return blur_axis_run<2>(in, out, n0, n1, n2, axis, wts, s);
+      case 3: return blur_axis_run<3>(in, out, n0, n1, n2, axis, wts, s);
+      case 4: return blur_axis_run<4>(in, out, n0, n1, n2, axis, wts, s);
+      case 5: return blur_axis_run<5>(in, out, n0, n1, n2, axis, wts, s);
+      case 6: return blur_axis_run<6>(in, out, n0, n1, n2, axis, wts, s);
+      default: break;
+    }
+  }
   const int64_t n = (int64_t)n0 * n1 * n2;
   hipLaunchKernelGGL(k_blur_axis, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, n0, n1, n2, axis, wts, radius);
   return hipGetLastError();
