@@ -232,8 +232,12 @@ def test_first_iteration_moves_at_most_eta_over_two():
     pr.close()
 
 
+# Blur radii ceil(3 s / 2), applied at full resolution: 6 and 3; 3; 5 and 3;
+# 8 (the one-output-per-thread form), 4 and 2; 6, 4 and 2.  Most of these n0
+# and n1 end in a partial run of eight outputs.
 @pytest.mark.parametrize("shape,scales", [((48, 56, 40), [4.0, 2.0, 1.0]), ((23, 19, 37), [2.0, 1.0]),
-                                          ((33, 64, 70), [3.0, 1.5])])
+                                          ((33, 64, 70), [3.0, 1.5]), ((40, 44, 52), [5.0, 2.5, 1.2]),
+                                          ((29, 21, 37), [4.0, 2.5, 1.2])])
 def test_pyramid_levels_match_oracle(shape, scales):
     p = synth.tissue_pair(shape, seed=51, bias_sigma=6.0, field_sigma=4.0, field_max=2.0)
     pr = new_pair(p.fixed, p.moving)
