@@ -10,7 +10,7 @@ namespace fa {
 // clamp(v, lo, hi) for lo <= hi as one v_med3_f32.  The median selects one of
 // its three operands, so for every non-NaN v the result is fminf(fmaxf(v, lo),
 // hi) bit for bit; that form costs a NaN-quieting max per operand on this
-// target besides the max and the min.  A quiet-NaN v gives lo in both forms.
+// target besides the max and the min.
 __device__ __forceinline__ float clamp_med3(float v, float lo, float hi) {
   return __builtin_amdgcn_fmed3f(v, lo, hi);
 }
