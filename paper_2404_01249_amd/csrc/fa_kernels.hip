@@ -1855,18 +1855,39 @@ __global__ void __launch_bounds__(256) k_blur_x(const float* __restrict__ in, fl
   out[row + x] = s;
 }
 
+// Voxel (z, y, x) and flat index i of this thread in an n0 x n1 x n2 launch:
+// on a (n2 / blockDim, n1, n0) grid (G3) from the block indices, with no
+// integer divisions; else from a flat index.  False past the end of a row or
+// of the volume.
+template <bool G3>
+__device__ __forceinline__ bool grid_voxel(int n0, int n1, int n2, int& z, int& y, int& x, int& i) {
+  if constexpr (G3) {
+    x = blockIdx.x * blockDim.x + threadIdx.x;
+    y = blockIdx.y;
+    z = blockIdx.z;
+    i = (z * n1 + y) * n2 + x;
+    return x < n2;
+  } else {
+    i = blockIdx.x * blockDim.x + threadIdx.x;
+    x = i % n2;
+    y = (i / n2) % n1;
+    z = i / (n1 * n2);
+    return i < n0 * n1 * n2;
+  }
+}
+
 __device__ __forceinline__ float aligned_pos(int i, int nin, int nout) {
   return nout > 1 ? (float)(i * (nin - 1)) / (float)(nout - 1) : 0.0f;
 }
 
+template <bool G3>
 __global__ void k_resample(const float* __restrict__ in, float* __restrict__ out, int ni0, int ni1,
                            int ni2, int no0, int no1, int no2, int nch, float rho0, float rho1,
                            float rho2) {
   const int No = no0 * no1 * no2;
   const int Ni = ni0 * ni1 * ni2;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= No) return;
-  const int x = i % no2, y = (i / no2) % no1, z = i / (no1 * no2);
+  int z, y, x, i;
+  if (!grid_voxel<G3>(no0, no1, no2, z, y, x, i)) return;
   const Corners c = make_corners(ni0, ni1, ni2, aligned_pos(z, ni0, no0), aligned_pos(y, ni1, no1),
                                  aligned_pos(x, ni2, no2));
   out[i] = rho0 * tri(in, c);
@@ -1876,12 +1897,12 @@ __global__ void k_resample(const float* __restrict__ in, float* __restrict__ out
   }
 }
 
+template <bool G3>
 __global__ void k_warp(const float* __restrict__ img, const float* __restrict__ d,
                        float* __restrict__ out, int n0, int n1, int n2) {
   const int N = n0 * n1 * n2;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int x = i % n2, y = (i / n2) % n1, z = i / (n1 * n2);
+  int z, y, x, i;
+  if (!grid_voxel<G3>(n0, n1, n2, z, y, x, i)) return;
   const Cell8 c = cell8_at(n0, n1, n2, z, y, x, d[i], d[N + i], d[2 * N + i]);
   Gather g;
   gather_issue(img, c, g);
@@ -2351,15 +2372,24 @@ hipError_t launch_blur_axis(const float* in, float* out, int n0, int n1, int n2,
 hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int nin2, int nout0,
                            int nout1, int nout2, int nch, float rho0, float rho1, float rho2,
                            hipStream_t s) {
-  const int64_t n = (int64_t)nout0 * nout1 * nout2;
-  hipLaunchKernelGGL(k_resample, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, nin0, nin1, nin2, nout0,
-                     nout1, nout2, nch, rho0, rho1, rho2);
+  if (nout0 <= 65535 && nout1 <= 65535) {   // grid z and y hold n0 and n1
+    hipLaunchKernelGGL(k_resample<true>, dim3(grid1(nout2, 256), nout1, nout0), dim3(256), 0, s, in, out, nin0,
+                       nin1, nin2, nout0, nout1, nout2, nch, rho0, rho1, rho2);
+  } else {
+    const int64_t n = (int64_t)nout0 * nout1 * nout2;
+    hipLaunchKernelGGL(k_resample<false>, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, nin0, nin1, nin2,
+                       nout0, nout1, nout2, nch, rho0, rho1, rho2);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_warp(const float* img, const float* d, float* out, int n0, int n1, int n2, hipStream_t s) {
-  const int64_t n = (int64_t)n0 * n1 * n2;
-  hipLaunchKernelGGL(k_warp, dim3(grid1(n, 256)), dim3(256), 0, s, img, d, out, n0, n1, n2);
+  if (n0 <= 65535 && n1 <= 65535) {
+    hipLaunchKernelGGL(k_warp<true>, dim3(grid1(n2, 256), n1, n0), dim3(256), 0, s, img, d, out, n0, n1, n2);
+  } else {
+    const int64_t n = (int64_t)n0 * n1 * n2;
+    hipLaunchKernelGGL(k_warp<false>, dim3(grid1(n, 256)), dim3(256), 0, s, img, d, out, n0, n1, n2);
+  }
   return hipGetLastError();
 }
 
