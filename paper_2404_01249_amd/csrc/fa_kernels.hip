@@ -1201,6 +1201,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
   for (int k0 = 0; k0 < KQ; k0 += KB) {
     bool qok[KB];
     float qd0[KB], qd1[KB], qd2[KB], qf[KB];
+    __builtin_amdgcn_s_setprio(2);   // as in the march: the batch's loads leave first
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int c = tid + (k0 + j) * NT;
@@ -1224,6 +1225,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
                                  qd0[j], qd1[j], qd2[j]);
       gather_issue(A.moving_pad, c8, gq[j]);
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int c = tid + (k0 + j) * NT;
