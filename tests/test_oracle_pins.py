@@ -353,6 +353,31 @@ def test_gaussian_weights(sigma):
     assert np.argmax(w) == R
 
 
+@pytest.mark.parametrize("sigma", [0.4, 0.5, 1.0, 2.0, 6.0])
+def test_gaussian_tap_values_match_independent_sampled_gaussians(sigma):
+    """Tap values against two independent samplings of the same kernel:
+    the impulse response of scipy.ndimage.gaussian_filter1d (truncate chosen
+    so its radius int(truncate sigma + 1/2) is ceil(3 sigma)) and
+    scipy.signal.windows.gaussian normalised to sum 1.  A sigma-for-sigma^2
+    slip (equal at sigma = 1 only) or a wrong radius fails here."""
+    from scipy.signal import windows
+    s = float(np.float32(sigma))     # the library receives sigma as float32
+    R = math.ceil(3 * s)
+    w = O.gaussian_weights(sigma)
+    impulse = np.zeros(4 * R + 3)
+    impulse[2 * R + 1] = 1.0
+    resp = ndi.gaussian_filter1d(impulse, s, mode="constant", truncate=R / s)
+    ref1 = resp[R + 1: 3 * R + 2]
+    assert np.count_nonzero(resp) == 2 * R + 1
+    np.testing.assert_allclose(w, ref1, rtol=1e-13, atol=0)
+    g = windows.gaussian(2 * R + 1, std=s, sym=True)
+    np.testing.assert_allclose(w, g / g.sum(), rtol=1e-13, atol=0)
+    # the ratio of neighbouring taps is exp(-(2k+1) / (2 sigma^2)), computed here
+    # from the definition rather than from the oracle's own expression
+    k = np.arange(0, R)
+    np.testing.assert_allclose(w[R + k + 1] / w[R + k], np.exp(-(2 * k + 1) / (2 * s * s)), rtol=1e-12)
+
+
 @pytest.mark.parametrize("sigma", [0.5, 1.0, 2.0])
 def test_gaussian_matches_scipy_correlate_nearest(sigma):
     """scipy.ndimage.correlate1d with mode='nearest' is replicate padding."""
@@ -579,3 +604,42 @@ def test_small_registration_descends_and_stays_diffeomorphic():
     J0 = O.lncc_forward(p.fixed, p.moving, 5, 1e-5)[1]
     J1 = O.lncc_forward(p.fixed, O.warp_image(p.moving, d), 5, 1e-5)[1]
     assert J1 < J0
+
+
+def test_level_transition_carries_adam_state_and_step_count():
+    """Section 4.5: the warp and the optimiser state are upsampled to the next
+    level, and the step count continues.  Two levels at scale 1 have the same
+    grid, where corner-aligned upsampling is exactly the identity (positions
+    i (n-1)/(n-1) = i, rho = 1), so splitting a run into two levels must give
+    the single-level run bitwise.  Resetting m, v or t at the transition would
+    change every later iteration (checked below by planting each reset)."""
+    from paper_2404_01249_amd import synth
+    p = synth.blobs_pair((9, 10, 11), seed=37, n_blobs=5, sigma_range=(1.5, 3.0), field_sigma=3.0, field_max=1.5)
+    P = O.Params(eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=3)
+    d1, l1, t1 = O.register(p.fixed, p.moving, [1.0], [7], P)
+    d2, l2, t2 = O.register(p.fixed, p.moving, [1.0, 1.0], [3, 4], P)
+    assert t1 == t2 == 7
+    assert np.array_equal(d1, d2)
+    assert np.array_equal(np.asarray(l1), np.asarray(l2))
+
+    # the pin has power: each planted reset moves the result
+    real_up, real_iter = O.fireants64.upsample_state, O.fireants64.iterate
+
+    def reset_moments(d, m, v, shape_f):
+        d, m, v = real_up(d, m, v, shape_f)
+        return d, np.zeros_like(m), np.zeros_like(v)
+
+    calls = {"n": 0}
+
+    def restart_t(fixed, moving, d, m, v, t, P_):
+        calls["n"] += 1
+        return real_iter(fixed, moving, d, m, v, t if calls["n"] <= 3 else t - 3, P_)
+
+    for name, fn in (("upsample_state", reset_moments), ("iterate", restart_t)):
+        setattr(O.fireants64, name, fn)
+        try:
+            d3, _, _ = O.register(p.fixed, p.moving, [1.0, 1.0], [3, 4], P)
+        finally:
+            setattr(O.fireants64, "upsample_state", real_up)
+            setattr(O.fireants64, "iterate", real_iter)
+        assert np.abs(d3 - d1).max() > 1e-6, name
