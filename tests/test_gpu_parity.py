@@ -371,6 +371,39 @@ def test_batched_pairs_match_single_runs(fused):
         pr.close()
 
 
+def check_run_against_oracle(loss, d, d_ref, loss_ref, label=""):
+    """The run tolerances of a registration against the oracle (loss history
+    and final field; see test_random_configurations_match_oracle)."""
+    rel = np.abs(np.asarray(loss, np.float64) - np.asarray(loss_ref)) / np.maximum(np.abs(loss_ref), 1e-12)
+    epe = np.sqrt(((d - d_ref) ** 2).sum(0))
+    q = float(np.quantile(epe, 0.999))
+    print(f"{label}: loss rel max {rel.max():.2e}, endpoint diff mean {epe.mean():.2e} 99.9% {q:.2e}")
+    assert rel[0] <= 1e-5 and rel.max() <= 1e-3, label
+    assert epe.mean() <= 1e-3 and q <= 0.05, label
+
+
+UNEVEN_PROBLEMS = [((21, 37, 45), 73), ((40, 48, 56), 74), ((30, 12, 50), 75)]
+UNEVEN_CFGS = [(0, dict(eta=0.5), [2.0, 1.0], [5, 4]),
+               (1, dict(eta=3.0), [2.0, 1.0], [3, 6]),
+               (1, dict(eta=1.0, window=3), [1.0], [7]),
+               (2, dict(eta=0.25, use_jac=True), [2.0, 1.0], [4, 2]),
+               (0, dict(eta=2.0, sigma_warp=0.0), [4.0, 2.0, 1.0], [2, 3, 2]),
+               (1, dict(eta=0.5, window=7, sigma_grad=1.5), [2.0, 1.0], [2, 3]),
+               (2, dict(eta=1.0), [1.0], [9])]
+_UNEVEN_ORACLE = {}
+
+
+def uneven_oracle_run(i):
+    """The oracle's registration of UNEVEN_CFGS[i] (computed once)."""
+    if i not in _UNEVEN_ORACLE:
+        k, kw, sc, it = UNEVEN_CFGS[i]
+        fixed, moving, _ = make_problem(*UNEVEN_PROBLEMS[k])
+        P = O.Params(**kw)
+        d_ref, loss_ref, _ = O.register(fixed, moving, sc, it, P)
+        _UNEVEN_ORACLE[i] = (d_ref, loss_ref)
+    return _UNEVEN_ORACLE[i]
+
+
 @pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graphs"])
 def test_fused_batch_of_uneven_pairs_matches_single_runs(graphs):
     """Batched launches over pairs that differ in size (brick and march
@@ -378,19 +411,13 @@ def test_fused_batch_of_uneven_pairs_matches_single_runs(graphs):
     composition with gathers), smoothing, schedule and use_jac, advanced a few
     iterations per call so that the launch tables change as pairs change
     level or finish: every pair gives the field of its run alone, bitwise
-    (each voxel's arithmetic does not depend on the launch shape).  With
-    graphs, the first iteration of each call runs eagerly and the other two
-    replay the captured graph, between the calls' own eager work."""
+    (each voxel's arithmetic does not depend on the launch shape), and the
+    oracle's registration to the run tolerances.  With graphs, the first
+    iteration of each call runs eagerly and the other two replay the captured
+    graph, between the calls' own eager work."""
     from paper_2404_01249_amd import run_batch
-    problems = [make_problem((21, 37, 45), seed=73), make_problem((40, 48, 56), seed=74),
-                make_problem((30, 12, 50), seed=75)]
-    cfgs = [(0, dict(eta=0.5), [2.0, 1.0], [5, 4]),
-            (1, dict(eta=3.0), [2.0, 1.0], [3, 6]),
-            (1, dict(eta=1.0, window=3), [1.0], [7]),
-            (2, dict(eta=0.25, use_jac=True), [2.0, 1.0], [4, 2]),
-            (0, dict(eta=2.0, sigma_warp=0.0), [4.0, 2.0, 1.0], [2, 3, 2]),
-            (1, dict(eta=0.5, window=7, sigma_grad=1.5), [2.0, 1.0], [2, 3]),
-            (2, dict(eta=1.0), [1.0], [9])]
+    problems = [make_problem(*pr) for pr in UNEVEN_PROBLEMS]
+    cfgs = UNEVEN_CFGS
     ref = []
     for k, kw, sc, it in cfgs:
         fixed, moving, _ = problems[k]
@@ -417,7 +444,10 @@ def test_fused_batch_of_uneven_pairs_matches_single_runs(graphs):
         np.testing.assert_allclose(pr.loss_history(), loss, rtol=1e-6, atol=0)
         got = pr.field()
         torch.cuda.synchronize()
-        assert np.array_equal(host(got), field), i
+        d = host(got)
+        assert np.array_equal(d, field), i
+        d_ref, loss_ref = uneven_oracle_run(i)
+        check_run_against_oracle(pr.loss_history(), d, d_ref, loss_ref, label=f"batch pair {i} {cfgs[i]}")
         pr.close()
 
 
