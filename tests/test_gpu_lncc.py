@@ -140,3 +140,69 @@ def test_blobs128_against_oracle_and_plain_autograd(window):
     assert abs(float(Lp.detach()) - L_ref) <= 1e-3 * abs(L_ref)
     assert rel_l2(host(gp[0]), g_ref) <= 2e-2
     lncc.close()
+
+
+def fd_gradient_at(fixed, moving, d, y, c, window, eps, h):
+    """FP64 central difference (h) of the oracle's cost in d_c(y).
+
+    Moving d_c(y) changes the warped image J only at y, and the cost only
+    through cc at the centres whose window holds y.  Those windows lie within
+    2r of y, so the cost difference is the oracle's cc summed over those
+    centres on a crop of y +- 2r (clipped at the volume's faces, so every
+    window is the volume's own), divided by the volume's voxel count N."""
+    r = window // 2
+    n = fixed.shape
+    lo = [max(0, y[a] - 2 * r) for a in range(3)]
+    hi = [min(n[a], y[a] + 2 * r + 1) for a in range(3)]
+    crop = tuple(slice(lo[a], hi[a]) for a in range(3))
+    I = fixed[crop].astype(np.float64)
+    pos = O.identity_grid(I.shape) + np.asarray(lo, np.float64)[:, None, None, None] + \
+        d[(slice(None),) + crop].astype(np.float64)
+    J = O.trilinear(moving, pos)
+    yl = tuple(y[a] - lo[a] for a in range(3))
+    cen = tuple(slice(max(0, y[a] - r) - lo[a], min(n[a], y[a] + r + 1) - lo[a]) for a in range(3))
+
+    def cost_part(delta):
+        p = pos[(slice(None),) + yl].copy()
+        p[c] += delta
+        Jp = J.copy()
+        Jp[yl] = O.trilinear(moving, p.reshape(3, 1, 1, 1))[0, 0, 0]
+        return -O.lncc_forward(I, Jp, window, eps)[0][cen].sum() / fixed.size
+
+    return (cost_part(h) - cost_part(-h)) / (2.0 * h)
+
+
+@pytest.mark.parametrize("window", [5, 9])
+def test_blobs128_gradient_against_central_differences(window):
+    """The fused gradient at 128^3 against FP64 central differences of the
+    cost (h = 1e-3) at 64 seeded voxels, all three components.  Voxels whose
+    sample x + d(x) lies within 2h of a cell boundary along any axis are
+    redrawn: there the trilinear derivative jumps and a difference quotient
+    does not measure it."""
+    print(f"lncc blobs128 finite differences w={window}", flush=True)
+    h = 1e-3
+    p = synth.load("blobs128")
+    d = synth.smooth_field(p.fixed.shape, 3, sigma=6.0, max_norm=2.0)
+    lncc = LNCC(p.fixed.shape, window=window)
+    _, g = lncc.loss_and_grad(dev(p.fixed), dev(p.moving), dev(d))
+    g = host(g)
+    lncc.close()
+    moving = p.moving.astype(np.float64)
+    rng = np.random.default_rng(128 + window)
+    picked = []
+    while len(picked) < 64:
+        y = tuple(int(rng.integers(0, n)) for n in p.fixed.shape)
+        frac = np.asarray([d[a][y] for a in range(3)], np.float64) % 1.0
+        if np.all((frac > 2 * h) & (frac < 1 - 2 * h)):
+            picked.append(y)
+    got, ref = [], []
+    for y in picked:
+        for c in range(3):
+            got.append(g[(c,) + y])
+            ref.append(fd_gradient_at(p.fixed, moving, d, y, c, window, 1e-5, h))
+    got, ref = np.asarray(got), np.asarray(ref)
+    err = rel_l2(got, ref)
+    print(f"finite differences w={window}: rel L2 {err:.2e}, max abs {np.abs(got - ref).max():.2e} "
+          f"of max {np.abs(ref).max():.2e}", flush=True)
+    assert err <= TOL_G
+    assert np.abs(got - ref).max() <= TOL_G * np.abs(ref).max()
