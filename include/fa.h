@@ -76,7 +76,8 @@ typedef struct {
  * cc_eps 1e-5, beta1 0.9, beta2 0.999, adam_eps 1e-8, use_jac 0. */
 fa_status fa_params_default(fa_params* out);
 
-/* Create a registration pair.
+/* Create a registration pair: the fixed image I_f and moving image I_m of
+ * Eq. (image-reg), which are Algorithm 1's first two inputs.
  *   fixed_dev, moving_dev: device pointers to float32 volumes of `shape`;
  *     copied on `hip_stream` (stream order), so the caller may release them
  *     once that copy has run.
@@ -93,7 +94,11 @@ fa_status fa_pair_create(const float* fixed_dev, const float* moving_dev, fa_sha
  * sigma = s_l/2 (none at s_l = 1) and resampled trilinearly at corner-aligned
  * positions (Section 4.5).  scales and iters are host arrays of n_levels
  * entries; scales >= 1; iters >= 0; every level dimension >= 2.
- * May be called again to restart.  Enqueued; does not synchronise. */
+ * May be called again to restart.  Not enqueued like the other calls: it
+ * synchronises the pair's stream (a previous schedule's pyramid is released
+ * first) and allocates device memory with hipMalloc where the new schedule
+ * needs more than the pair holds; the pyramid build and the state reset are
+ * then enqueued on the stream. */
 fa_status fa_pair_set_schedule(fa_pair pair, int n_levels, const float* scales, const int* iters);
 
 /* Run up to max_iters iterations of Algorithm 1 (crossing level boundaries
@@ -103,19 +108,24 @@ fa_status fa_pair_set_schedule(fa_pair pair, int n_levels, const float* scales, 
 fa_status fa_pair_step(fa_pair pair, int max_iters, int* iters_done, int* finished);
 
 /* Copy the loss history (one value per completed iteration: the cost
- * -mean(LNCC) at the warp before that iteration's update) to host memory.
+ * -mean(LNCC) at the warp before that iteration's update, Algorithm 1's U_i
+ * with C of Eq. (image-reg)) to host memory.
  * Synchronises the stream.  Writes min(capacity, count) values; *n_written
  * receives that number. */
 fa_status fa_pair_get_loss(fa_pair pair, float* host_out, int capacity, int* n_written);
 
-/* Copy the current displacement (at the current level) into dev_out.
+/* Copy the current displacement d of phi = id + d (Algorithm 1's output once
+ * the schedule is finished; the warp at the current level before that) into
+ * dev_out.
  * layout 0: SoA [3][n0][n1][n2]; layout 1: [n0][n1][n2][3].  *level (0-based)
  * and *shape receive the level and its size (either may be NULL); with
  * dev_out NULL only those are returned.  Enqueued. */
 fa_status fa_pair_get_field(fa_pair pair, float* dev_out, int layout, int* level, fa_shape* shape);
 
-/* J = I_m o phi at the current level (trilinear, zero outside the grid) into
- * dev_out ([n0][n1][n2] of the current level).  Enqueued. */
+/* J = I_m o phi at the current level, the warped image whose cost Algorithm 1
+ * evaluates (Eq. (image-reg); the pushforward image of Section 4.4.3),
+ * sampled trilinearly with zero outside the grid, into dev_out ([n0][n1][n2]
+ * of the current level).  Enqueued. */
 fa_status fa_pair_get_warped(fa_pair pair, float* dev_out);
 
 /* Destroy a pair (synchronises its stream, frees everything).  NULL is a no-op. */
