@@ -53,6 +53,34 @@ fa_status fa_lncc_eval(fa_lncc h, const float* fixed, const float* moving, const
 /* Destroy (synchronises the stream).  NULL is a no-op. */
 void fa_lncc_destroy(fa_lncc h);
 
+/* Size in bytes of the library's fixed device scratch array used by
+ * fa_lncc_eval_noalloc (one copy per GPU, held until the process ends). */
+#define FA_LNCC_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* fa_lncc_eval without an evaluator, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It computes exactly what fa_lncc_create(shape, window,
+ * cc_eps, hip_stream) followed by fa_lncc_eval(fixed, moving, d, loss_dev,
+ * grad_dev, grad_scale_dev) computes (same kernels, same launch shapes, so
+ * the same bits), with arguments as documented there.
+ *
+ * It calls no hipMalloc, hipFree or other allocating routine.  Every buffer
+ * besides the caller's inputs and outputs (control block, reduction partials,
+ * zero-bordered copy of the moving image) lives in a fixed device array of
+ * FA_LNCC_NOALLOC_SCRATCH_BYTES; a call needs about 4 (n0+4)(n1+4)(n2+4)
+ * bytes of it plus a few KB (160x192x224 takes 29.3 MB).  A larger volume is
+ * rejected with FA_EINVAL before any work is enqueued.  The first call on a
+ * device looks up the array's address on that device (hipGetSymbolAddress).
+ *
+ * Every call on one GPU shares that GPU's array, and each call overwrites
+ * what the last one left there before reading it.  Calls on one GPU that
+ * overlap in time (different streams, or different host threads without
+ * ordering) race on the array and must be serialised by the caller.
+ * Enqueued on hip_stream (NULL = null stream); returns an fa_status. */
+fa_status fa_lncc_eval_noalloc(fa_shape shape, int window, float cc_eps, const float* fixed, const float* moving,
+                               const float* d, float* loss_dev, float* grad_dev, const float* grad_scale_dev,
+                               void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

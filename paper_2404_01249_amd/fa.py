@@ -92,6 +92,7 @@ SIGNATURES = {
     "fa_lncc_create": (_I, [fa_shape, _I, ctypes.c_float, _P, ctypes.POINTER(_P)]),
     "fa_lncc_eval": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "fa_lncc_destroy": (None, [_P]),
+    "fa_lncc_eval_noalloc": (_I, [fa_shape, _I, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P]),
     "fa_warp_labels": (_I, [_P, _P, fa_shape, _P, _P]),
     "fa_label_overlap": (_I, [_P, _P, _I64, _I, _I64P, _P]),
     "fa_jacobian_det": (_I, [_P, fa_shape, _P, _I64P, _I64P, _P]),
@@ -284,6 +285,13 @@ def fa_lncc_eval(h: int, fixed, moving, d, loss_dev=None, grad_dev=None, grad_sc
 def fa_lncc_destroy(h: int):
     if h:
         load_library().fa_lncc_destroy(h)
+
+
+def fa_lncc_eval_noalloc(shape, window: int, cc_eps: float, fixed, moving, d, loss_dev=None, grad_dev=None,
+                         grad_scale_dev=None, stream=None):
+    _check(load_library().fa_lncc_eval_noalloc(fa_shape(*[int(x) for x in shape]), int(window), float(cc_eps),
+                                               _ptr(fixed), _ptr(moving), _ptr(d), _ptr(loss_dev), _ptr(grad_dev),
+                                               _ptr(grad_scale_dev), _stream_handle(stream)))
 
 
 # ---- include/fa_eval.h --------------------------------------------------------

@@ -181,3 +181,16 @@ def test_compose_fields_rejects_bad_arguments(lib):
     assert lib.fa_compose_fields(None, p(32), shp, p(64), None) == fa.FA_EINVAL
     assert lib.fa_compose_fields(p(16), p(32), shp, p(32), None) == fa.FA_EINVAL   # out aliases d
     assert lib.fa_compose_fields(p(16), p(32), fa.fa_shape(1, 5, 6), p(64), None) == fa.FA_ESHAPE
+
+
+def test_noalloc_lncc_rejects_bad_arguments_before_device_work(lib):
+    fn = lib.fa_lncc_eval_noalloc
+    ok = fa.fa_shape(8, 8, 8)
+    # a volume whose padded copy exceeds the fixed scratch array (204^3 floats > 32 MiB)
+    assert fn(fa.fa_shape(200, 200, 200), 5, 1e-5, 1, 2, 3, 4, 5, None, None) == fa.FA_EINVAL
+    assert "too large" in fa.fa_last_error()
+    assert fn(ok, 4, 1e-5, 1, 2, 3, 4, 5, None, None) == fa.FA_EINVAL          # even window
+    assert fn(ok, 5, -1.0, 1, 2, 3, 4, 5, None, None) == fa.FA_EINVAL         # negative eps
+    assert fn(ok, 5, 1e-5, None, 2, 3, 4, 5, None, None) == fa.FA_EINVAL      # null input
+    assert fn(ok, 5, 1e-5, 1, 2, 3, None, None, None, None) == fa.FA_EINVAL   # no output
+    assert fn(fa.fa_shape(1, 8, 8), 5, 1e-5, 1, 2, 3, 4, 5, None, None) == fa.FA_ESHAPE
