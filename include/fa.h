@@ -58,7 +58,7 @@ typedef struct {
   float eta;          /* step size: max |u| per iteration is eta/2 voxels (Appendix E,
                          LP(v) <= 2 sup|v|/|dx| with dx = 1 voxel); > 0            */
   float sigma_grad;   /* Gaussian on the Adam direction, voxels of the level;
-                         <= 0 disables; radius ceil(3 sigma) must be <= 6          */
+                         <= 0 disables; radius ceil(3 sigma) must be <= 24         */
   float sigma_warp;   /* Gaussian on the composed displacement; same rules         */
   int   cc_window;    /* LNCC window w = 2r+1; odd, 1..9                            */
   float cc_eps;       /* added to the product of the sum-form window variances; >= 0 */

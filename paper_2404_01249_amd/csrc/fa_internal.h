@@ -92,6 +92,10 @@ struct GaussArgs {
   float eta;
   int n0, n1, n2;
   int zc, tiles_y, tiles_x;
+  // radius above kMaxRadius only (launch_gauss): a [3][N] scratch field
+  // distinct from in and out, and the device tap table {1}
+  float* wide_tmp;
+  const float* one_tap;
 };
 
 // ---- batched launches ----------------------------------------------------
@@ -163,6 +167,10 @@ constexpr int kPad = 2;
 inline int64_t padded_voxels(int n0, int n1, int n2) {
   return (int64_t)(n0 + 2 * kPad) * (n1 + 2 * kPad) * (n2 + 2 * kPad);
 }
+// Gaussian radii: the streaming and brick kernels take 0..kMaxRadius as a
+// template parameter; launch_gauss runs radii up to kMaxWideRadius through
+// separable passes with a run-time radius (GaussArgs::wide_tmp).
 constexpr int kMaxRadius = 6;
+constexpr int kMaxWideRadius = 24;
 
 }  // namespace fa

@@ -366,6 +366,7 @@ struct fa_inverse_s {
   float* v = nullptr;
   float* a = nullptr;      // Adam direction
   float* tmp = nullptr;    // smoothed direction, then the composed field
+  float* wide = nullptr;   // [3][cap] scratch of the smoothing passes with a radius above 6
   unsigned long long* acc = nullptr;   // splat accumulator [3][n], zero between iterations
   Ctl* ctl = nullptr;
   float* loss_hist = nullptr;
@@ -389,7 +390,7 @@ void free_levels(fa_inverse H) {
 
 void free_all(fa_inverse H) {
   free_levels(H);
-  float* fb[] = {H->in_d, H->e, H->m, H->v, H->a, H->tmp, H->loss_hist, H->scalar, H->wts};
+  float* fb[] = {H->in_d, H->e, H->m, H->v, H->a, H->tmp, H->wide, H->loss_hist, H->scalar, H->wts};
   for (float* b : fb)
     if (b) (void)hipFree(b);
   if (H->acc) (void)hipFree(H->acc);
@@ -459,6 +460,8 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g1.in = H->a;
   g1.out = H->tmp;
   g1.wts = H->wts + H->off_g;
+  g1.wide_tmp = H->wide;
+  g1.one_tap = H->wts + H->off_one;
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
@@ -478,6 +481,8 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g3.in = H->tmp;
   g3.out = H->e;
   g3.wts = H->wts + H->off_w;
+  g3.wide_tmp = H->wide;
+  g3.one_tap = H->wts + H->off_one;
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;
@@ -576,8 +581,9 @@ fa_status fa_inverse_set_schedule(fa_inverse H, int n_levels, const float* scale
 
   // state (sized for the largest level) and the splat accumulator
   const int64_t need = std::max(nmax, H->n);   // the blur scratch below spans 5 input-sized volumes
-  if (need > H->cap) {
-    float** bufs[] = {&H->e, &H->m, &H->v, &H->a, &H->tmp};
+  const bool wide = H->rg > fa::kMaxRadius || H->rw > fa::kMaxRadius;
+  if (need > H->cap || (wide && !H->wide)) {
+    float** bufs[] = {&H->e, &H->m, &H->v, &H->a, &H->tmp, &H->wide};
     for (float** b : bufs) {
       if (*b) (void)hipFree(*b);
       *b = nullptr;
@@ -587,7 +593,7 @@ fa_status fa_inverse_set_schedule(fa_inverse H, int n_levels, const float* scale
     if (H->partials) (void)hipFree(H->partials);
     H->partials = nullptr;
     H->cap = 0;
-    for (float** b : bufs) FA_TRY(ialloc(b, (size_t)(3 * need), "state"));
+    for (int k = 0; k < (wide ? 6 : 5); ++k) FA_TRY(ialloc(bufs[k], (size_t)(3 * need), "state"));
     FA_TRY(ialloc(&H->acc, (size_t)(3 * need), "splat accumulator"));
     FA_TRY(ialloc(&H->partials, (size_t)(2 * kInvMaxBlocks), "cost partials"));
     H->cap = need;

@@ -1794,6 +1794,75 @@ __global__ void k_fill(float* __restrict__ p, float value, int64_t n) {
   if (i < n) p[i] = value;
 }
 
+// ---- Gaussian smoothing of a field with a radius above kMaxRadius ----------
+// One separable pass of a 3-component field [3][n0][n1][n2] along one axis:
+// out_c(x) = sum_{k=-R..R} w[k+R] in_c(x + k e_axis), the index clamped to the
+// grid (replicate), the taps summed in that order.  The radius is a run-time
+// value up to kMaxWideRadius.  A workgroup stages its line segment (outputs
+// plus R on each side) in LDS once and every output reads its 2R+1 taps from
+// there.
+//
+// Along n2: a workgroup of 256 threads takes 256 consecutive voxels of one
+// row (grid: ceil(n2/256), n1, n0).
+__global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ in, float* __restrict__ out,
+                                                      int n0, int n1, int n2, const float* __restrict__ w, int R) {
+  extern __shared__ float wl[];   // [3][256 + 2R]
+  const int L = 256 + 2 * R;
+  const int x0 = blockIdx.x * 256, y = blockIdx.y, z = blockIdx.z;
+  const int64_t N = (int64_t)n0 * n1 * n2;
+  const int64_t row = ((int64_t)z * n1 + y) * n2;
+  for (int c = 0; c < 3; ++c)
+    for (int i = threadIdx.x; i < L; i += 256) {
+      const int xx = min(max(x0 - R + i, 0), n2 - 1);
+      wl[c * L + i] = in[c * N + row + xx];
+    }
+  __syncthreads();
+  const int x = x0 + threadIdx.x;
+  if (x >= n2) return;
+  for (int c = 0; c < 3; ++c) {
+    const float* src = wl + c * L + threadIdx.x;
+    float acc = w[0] * src[0];
+    for (int k = 1; k <= 2 * R; ++k) acc += w[k] * src[k];
+    out[c * N + row + x] = acc;
+  }
+}
+
+// Along n1 (axis 1) or n0 (axis 0): a workgroup of 64 x 4 threads takes 64
+// consecutive n2 columns and kWideRun consecutive positions along the axis
+// (grid: ceil(n2/64), ceil(n_axis/kWideRun), the remaining axis); thread
+// (lane, j) forms the outputs j, j + 4, ... of its column.
+constexpr int kWideRun = 32;
+template <int AX>
+__global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
+                                                       int n0, int n1, int n2, const float* __restrict__ w, int R) {
+  extern __shared__ float wl[];   // [3][kWideRun + 2R][64]
+  const int L = kWideRun + 2 * R;
+  const int lane = threadIdx.x & 63, j0 = threadIdx.x >> 6;
+  const int x = blockIdx.x * 64 + lane;
+  const int a0 = blockIdx.y * kWideRun;
+  const int na = AX == 0 ? n0 : n1;
+  const int other = blockIdx.z;   // y for AX == 0, z for AX == 1
+  const int64_t N = (int64_t)n0 * n1 * n2;
+  const int64_t astride = AX == 0 ? (int64_t)n1 * n2 : (int64_t)n2;
+  const int64_t base = AX == 0 ? (int64_t)other * n2 : (int64_t)other * n1 * n2;
+  const bool xin = x < n2;
+  for (int c = 0; c < 3; ++c)
+    for (int i = j0; i < L; i += 4) {
+      const int aa = min(max(a0 - R + i, 0), na - 1);
+      wl[(c * L + i) * 64 + lane] = xin ? in[c * N + base + aa * astride + x] : 0.0f;
+    }
+  __syncthreads();
+  if (!xin) return;
+  for (int j = j0; j < kWideRun && a0 + j < na; j += 4) {
+    for (int c = 0; c < 3; ++c) {
+      const float* src = wl + (c * L + j) * 64 + lane;
+      float acc = w[0] * src[0];
+      for (int k = 1; k <= 2 * R; ++k) acc += w[k] * src[k * 64];
+      out[c * N + base + (int64_t)(a0 + j) * astride + x] = acc;
+    }
+  }
+}
+
 __global__ void k_blur_axis(const float* __restrict__ in, float* __restrict__ out, int n0, int n1,
                             int n2, int axis, const float* __restrict__ w, int R) {
   const int N = n0 * n1 * n2;
@@ -2297,12 +2366,60 @@ hipError_t launch_gauss_batch(const BatchEntry<GaussArgs>* E, const int* owner, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
+hipError_t launch_gauss_narrow(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
   if (t.cube) return gauss_launch_cube(a, radius, epilogue, t, s);
   if (t.ty == 16 && t.tx == 32) return gauss_launch_tile<16, 32>(a, radius, epilogue, t, s);
   if (t.ty == 8 && t.tx == 32) return gauss_launch_tile<8, 32>(a, radius, epilogue, t, s);
   if (t.ty == 8 && t.tx == 64) return gauss_launch_tile<8, 64>(a, radius, epilogue, t, s);
   return hipErrorInvalidValue;
+}
+
+// Radius above kMaxRadius (sigma_grad or sigma_warp or the inverse's widths
+// above 2 voxels): three separable passes through a.wide_tmp, then the
+// single-tap launch of the epilogue (max norm, or loss record and step
+// count) from the smoothed field:
+//   in -> wide_tmp (n2), wide_tmp -> out (n1), out -> wide_tmp (n0),
+//   wide_tmp -> out with the epilogue.
+// Needs a.wide_tmp distinct from a.in and a.out, and a.in != a.out.
+hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
+  if (radius > kMaxWideRadius || !a.wide_tmp || a.wide_tmp == a.in || a.wide_tmp == a.out || a.in == a.out ||
+      (epilogue != EPI_SMOOTH_MAX && epilogue != EPI_STORE_FINAL && epilogue != EPI_STORE))
+    return hipErrorInvalidValue;
+  const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+  if (n0 > 65535 || n1 > 65535) return hipErrorInvalidValue;
+  const size_t shx = sizeof(float) * 3 * (256 + 2 * radius);
+  const size_t shyz = sizeof(float) * 3 * (kWideRun + 2 * radius) * 64;
+  k_field_wide_x<<<dim3((n2 + 255) / 256, n1, n0), dim3(256), shx, s>>>(a.in, a.wide_tmp, n0, n1, n2, a.wts,
+                                                                         radius);
+  k_field_wide_yz<1><<<dim3((n2 + 63) / 64, (n1 + kWideRun - 1) / kWideRun, n0), dim3(256), shyz, s>>>(
+      a.wide_tmp, a.out, n0, n1, n2, a.wts, radius);
+  k_field_wide_yz<0><<<dim3((n2 + 63) / 64, (n0 + kWideRun - 1) / kWideRun, n1), dim3(256), shyz, s>>>(
+      a.out, a.wide_tmp, n0, n1, n2, a.wts, radius);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GaussArgs b = a;
+  b.in = a.wide_tmp;
+  b.wts = a.one_tap;
+  // the epilogue launch runs the march with a single tap (any march tiling fits it)
+  Tiling tm = t;
+  if (tm.cube) tm = Tiling{};
+  if (tm.tx == 0) {
+    tm.ty = n1 >= 16 ? 16 : 8;
+    tm.tx = 32;
+    tm.tiles_y = (n1 + tm.ty - 1) / tm.ty;
+    tm.tiles_x = (n2 + tm.tx - 1) / tm.tx;
+    tm.zc = std::max(1, std::min(n0, (int)(((int64_t)n0 * tm.tiles_y * tm.tiles_x + 1023) / 1024)));
+    tm.chunks = (n0 + tm.zc - 1) / tm.zc;
+  }
+  b.zc = tm.zc;
+  b.tiles_y = tm.tiles_y;
+  b.tiles_x = tm.tiles_x;
+  return launch_gauss_narrow(b, 0, epilogue, tm, s);
+}
+
+hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
+  if (radius > kMaxRadius) return launch_gauss_wide(a, radius, epilogue, t, s);
+  return launch_gauss_narrow(a, radius, epilogue, t, s);
 }
 
 

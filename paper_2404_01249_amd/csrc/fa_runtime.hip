@@ -60,8 +60,8 @@ fa_status check_params(const fa_params* p) {
   if (!(p->adam_eps >= 0.0f) || !std::isfinite(p->adam_eps)) return fail(FA_EINVAL, "adam_eps must be finite and >= 0");
   if (!std::isfinite(p->sigma_grad) || !std::isfinite(p->sigma_warp))
     return fail(FA_EINVAL, "sigma_grad and sigma_warp must be finite");
-  if (tap_radius(p->sigma_grad) > fa::kMaxRadius || tap_radius(p->sigma_warp) > fa::kMaxRadius)
-    return fail(FA_EINVAL, "Gaussian radius ceil(3 sigma) must be <= 6 (sigma <= 2 voxels)");
+  if (tap_radius(p->sigma_grad) > fa::kMaxWideRadius || tap_radius(p->sigma_warp) > fa::kMaxWideRadius)
+    return fail(FA_EINVAL, "Gaussian radius ceil(3 sigma) must be <= 24 (sigma <= 8 voxels)");
   if (p->use_jac != 0 && p->use_jac != 1) return fail(FA_EINVAL, "use_jac must be 0 or 1");
   return FA_OK;
 }
@@ -127,6 +127,7 @@ struct fa_pair_s {
   float* v = nullptr;
   float* a = nullptr;         // Adam direction
   float* tmp = nullptr;       // smoothed direction s, then the composed d'
+  float* wide = nullptr;      // [3][cap] scratch of the smoothing passes with a radius above 6
   float* blur0 = nullptr;     // pyramid scratch (input size)
   float* blur1 = nullptr;
   Ctl* ctl = nullptr;
@@ -183,7 +184,7 @@ void free_levels(fa_pair P) {
 
 void free_all(fa_pair P) {
   free_levels(P);
-  float* fbufs[] = {P->in_fixed, P->in_moving, P->d, P->m, P->v, P->a, P->tmp, P->blur0,
+  float* fbufs[] = {P->in_fixed, P->in_moving, P->d, P->m, P->v, P->a, P->tmp, P->wide, P->blur0,
                     P->blur1, P->loss_hist, P->wts};
   for (float* b : fbufs)
     if (b) (void)hipFree(b);
@@ -309,6 +310,8 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g1.in = P->a;
   g1.out = P->tmp;
   g1.wts = P->wts + P->off_g;
+  g1.wide_tmp = P->wide;
+  g1.one_tap = P->wts + P->off_one;
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
@@ -338,6 +341,8 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g3.in = P->tmp;
   g3.out = P->d;
   g3.wts = P->wts + P->off_w;
+  g3.wide_tmp = P->wide;
+  g3.one_tap = P->wts + P->off_one;
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;
@@ -435,6 +440,10 @@ struct BatchLaunch {
   size_t ent_off;  // byte offsets of the entries and the owner array
   size_t own_off;
   int total;       // workgroups of the launch
+  // radius above 6: no batched form; each entry's launches run one after
+  // another from these host-side arguments instead
+  std::vector<fa::GaussArgs> singles;
+  std::vector<Tiling> single_t;
 };
 
 struct BatchTables {
@@ -536,6 +545,15 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
         taken[j] = 1;
         mem.push_back(j);
       }
+      if (its[i].radius[k] > fa::kMaxRadius) {
+        BatchLaunch bl{k + 1, its[i].tgs[k], its[i].radius[k], its[i].epi[k], 0, 0, 0};
+        for (size_t j : mem) {
+          bl.singles.push_back(its[j].g[k]);
+          bl.single_t.push_back(its[j].tgs[k]);
+        }
+        bt.launches.push_back(std::move(bl));
+        continue;
+      }
       if (!fa::gauss_batch_supported(its[i].radius[k], its[i].epi[k], its[i].tgs[k]))
         return fail(FA_EINVAL, "no batched smoothing launch for this radius, epilogue and tiling");
       std::vector<Tiling*> ts;
@@ -586,6 +604,11 @@ fa_status launch_batch_iteration(const std::vector<fa_pair>& live, const BatchTa
     if (bl.stage >= 1 && !jac_done) {
       for (int j : bt.jac) FA_TRY(launch_eulerian(live[j], live[j]->levels[live[j]->cur_level]));
       jac_done = true;
+    }
+    if (!bl.singles.empty()) {
+      for (size_t e = 0; e < bl.singles.size(); ++e)
+        FA_HIP(fa::launch_gauss(bl.singles[e], bl.param, bl.epi, bl.single_t[e], s));
+      continue;
     }
     const int* own = reinterpret_cast<const int*>(base + bl.own_off);
     if (bl.stage == 0) {
@@ -945,14 +968,16 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
   FA_HIP(hipMemcpyAsync(P->wts, P->wts_host.data(), P->wts_host.size() * sizeof(float),
                         hipMemcpyHostToDevice, P->stream));
 
-  if (nmax > P->cap) {
-    float** bufs[] = {&P->d, &P->m, &P->v, &P->a, &P->tmp};
+  const bool wide = P->rg > fa::kMaxRadius || P->rw > fa::kMaxRadius;
+  if (nmax > P->cap || (wide && !P->wide)) {
+    float** bufs[] = {&P->d, &P->m, &P->v, &P->a, &P->tmp, &P->wide};
     for (float** b : bufs) {
       if (*b) (void)hipFree(*b);
       *b = nullptr;
     }
     P->cap = 0;
-    for (float** b : bufs) FA_TRY(dalloc(b, (size_t)3 * nmax, "state"));
+    const int nb = wide ? 6 : 5;
+    for (int k = 0; k < nb; ++k) FA_TRY(dalloc(bufs[k], (size_t)3 * nmax, "state"));
     P->cap = nmax;
   }
   if (total_iters > P->loss_cap) {

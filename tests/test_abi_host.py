@@ -51,7 +51,8 @@ def _create_raw(lib, params, shape=(8, 8, 8), ptrs=(1, 2)):
 
 @pytest.mark.parametrize("field,value", [("cc_window", 4), ("cc_window", 11), ("cc_window", 0),
                                          ("eta", 0.0), ("eta", -1.0), ("use_jac", 2),
-                                         ("sigma_grad", 2.5), ("adam_beta1", 1.0), ("cc_eps", -1.0)])
+                                         ("sigma_grad", 8.5), ("sigma_warp", 100.0), ("adam_beta1", 1.0),
+                                         ("cc_eps", -1.0)])
 def test_invalid_params_rejected_before_device_work(lib, field, value):
     p = fa.fa_params_default()
     setattr(p, field, value)
@@ -194,3 +195,17 @@ def test_noalloc_lncc_rejects_bad_arguments_before_device_work(lib):
     assert fn(ok, 5, 1e-5, None, 2, 3, 4, 5, None, None) == fa.FA_EINVAL      # null input
     assert fn(ok, 5, 1e-5, 1, 2, 3, None, None, None, None) == fa.FA_EINVAL   # no output
     assert fn(fa.fa_shape(1, 8, 8), 5, 1e-5, 1, 2, 3, 4, 5, None, None) == fa.FA_ESHAPE
+
+
+@pytest.mark.parametrize("sigma", [2.5, 6.0, 8.0])
+def test_wide_gaussians_pass_validation(lib, sigma):
+    """Radii ceil(3 sigma) up to 24 (sigma <= 8 voxels) pass parameter
+    validation: creation gets past it (and, without a GPU, stops at the first
+    device call instead)."""
+    p = fa.fa_params_default()
+    p.sigma_grad = sigma
+    p.sigma_warp = sigma
+    st, h = _create_raw(lib, p)
+    assert st != fa.FA_EINVAL, fa.fa_last_error()
+    if h is not None:
+        lib.fa_pair_destroy(h)

@@ -50,10 +50,13 @@ def test_gradient_matches_oracle_at_the_iterate(shape):
     assert abs(U0 - U0r) <= 1e-5 * U0r and abs(U - Ur) <= 1e-5 * Ur
 
 
-def test_one_iteration_matches_oracle():
+@pytest.mark.parametrize("sigma_grad,sigma_warp", [(1.0, 0.5), (6.0, 0.4), (2.5, 3.0)])
+def test_one_iteration_matches_oracle(sigma_grad, sigma_warp):
+    """One iteration of the fit; the wider Gaussians (radii 18, 8 and 9) run
+    the separable passes with a run-time radius."""
     shape = (21, 37, 45)
     d = warp_field(shape, 102, 2.0)
-    P = F.Params(eta=0.5, sigma_grad=1.0, sigma_warp=0.5)
+    P = F.Params(eta=0.5, sigma_grad=sigma_grad, sigma_warp=sigma_warp)
     with Inverse(dev(d), eta=P.eta, sigma_grad=P.sigma_grad, sigma_warp=P.sigma_warp) as inv:
         inv.set_schedule([1.0], [1])
         assert inv.run() == 1

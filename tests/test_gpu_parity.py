@@ -55,6 +55,17 @@ def new_pair(fixed, moving, **kw):
     return pr
 
 
+def check_run_against_oracle(loss, d, d_ref, loss_ref, label=""):
+    """The run tolerances of a registration against the oracle (loss history
+    and final field; see test_random_configurations_match_oracle)."""
+    rel = np.abs(np.asarray(loss, np.float64) - np.asarray(loss_ref)) / np.maximum(np.abs(loss_ref), 1e-12)
+    epe = np.sqrt(((d - d_ref) ** 2).sum(0))
+    q = float(np.quantile(epe, 0.999))
+    print(f"{label}: loss rel max {rel.max():.2e}, endpoint diff mean {epe.mean():.2e} 99.9% {q:.2e}")
+    assert rel[0] <= 1e-5 and rel.max() <= 1e-3, label
+    assert epe.mean() <= 1e-3 and q <= 0.05, label
+
+
 SHAPES = [(21, 37, 45), (12, 131, 133), (7, 5, 6)]
 
 
@@ -183,10 +194,14 @@ def test_short_run_with_use_jac_matches_oracle():
 
 
 @pytest.mark.parametrize("eta,sigma_grad,sigma_warp", [(2.0, 0.3, 0.0), (3.0, 0.5, 1.0), (0.25, 0.0, 0.4),
-                                                      (1.0, 2.0, 2.0)])
+                                                      (1.0, 2.0, 2.0), (0.25, 6.0, 0.4), (1.0, 2.5, 3.0),
+                                                      (3.0, 8.0, 7.5)])
 def test_one_iteration_step_variants(eta, sigma_grad, sigma_warp):
     """Both composition paths (staged in LDS for eta <= 2, gathered beyond)
-    and Gaussian radii 0..6, from an injected state."""
+    and Gaussian radii 0..24, from an injected state: radii up to 6 run the
+    streaming kernels, wider ones (sigma_grad 6 and sigma_warp 0.4 are the
+    lung CT settings of the paper's EMPIRE10 runs) the separable passes with
+    a run-time radius, which here exceed every axis of the volume."""
     shape = (19, 33, 41)
     fixed, moving, d = make_problem(shape, seed=33)
     P = O.Params(eta=eta, sigma_grad=sigma_grad, sigma_warp=sigma_warp, window=3)
@@ -196,10 +211,30 @@ def test_one_iteration_step_variants(eta, sigma_grad, sigma_warp):
     pr.step(1)
     d1 = host(pr.state()[0])
     z = np.zeros((3,) + shape)
-    ref_d, _, _, _, ex = O.iterate(fixed, moving, d.astype(np.float64), z, z, 1, P)
+    ref_d, _, _, ref_L, ex = O.iterate(fixed, moving, d.astype(np.float64), z, z, 1, P)
     assert rel_l2(d1 - d, ref_d - d) <= TOL_G
     assert abs(pr.step_norm() - ex["M"]) <= TOL_G * ex["M"]
+    assert abs(pr.loss_history()[-1] - ref_L) <= TOL_L * abs(ref_L)
     pr.close()
+
+
+@pytest.mark.parametrize("shape", [(21, 37, 45), (40, 48, 56)])
+def test_run_with_lung_ct_smoothing_matches_oracle(shape):
+    """A two-level run with the paper's EMPIRE10 hyperparameters (eta 0.25,
+    sigma_grad 6, sigma_warp 0.4; Datasets and Evaluation Metrics, lung CT)
+    against the oracle: the radius-18 smoothing of the direction runs the
+    wide passes at both levels, the radius-2 warp smoothing the streaming or
+    brick kernels."""
+    fixed, moving, _ = make_problem(shape, seed=34)
+    kw = dict(eta=0.25, sigma_grad=6.0, sigma_warp=0.4, window=5)
+    scales, iters = [2.0, 1.0], [6, 4]
+    pr = new_pair(fixed, moving, **kw)
+    pr.set_schedule(scales, iters)
+    assert pr.run() == sum(iters)
+    loss, d = pr.loss_history(), host(pr.field())
+    pr.close()
+    d_ref, loss_ref, _ = O.register(fixed, moving, scales, iters, O.Params(**kw))
+    check_run_against_oracle(loss, d, d_ref, loss_ref, label=f"lung CT smoothing {shape}")
 
 
 @pytest.mark.parametrize("shape,sigma_grad,sigma_warp,eta", [((21, 37, 45), 1.0, 0.5, 0.5), ((40, 48, 56), 0.3, 0.0, 2.0),
@@ -371,17 +406,6 @@ def test_batched_pairs_match_single_runs(fused):
         pr.close()
 
 
-def check_run_against_oracle(loss, d, d_ref, loss_ref, label=""):
-    """The run tolerances of a registration against the oracle (loss history
-    and final field; see test_random_configurations_match_oracle)."""
-    rel = np.abs(np.asarray(loss, np.float64) - np.asarray(loss_ref)) / np.maximum(np.abs(loss_ref), 1e-12)
-    epe = np.sqrt(((d - d_ref) ** 2).sum(0))
-    q = float(np.quantile(epe, 0.999))
-    print(f"{label}: loss rel max {rel.max():.2e}, endpoint diff mean {epe.mean():.2e} 99.9% {q:.2e}")
-    assert rel[0] <= 1e-5 and rel.max() <= 1e-3, label
-    assert epe.mean() <= 1e-3 and q <= 0.05, label
-
-
 UNEVEN_PROBLEMS = [((21, 37, 45), 73), ((40, 48, 56), 74), ((30, 12, 50), 75)]
 UNEVEN_CFGS = [(0, dict(eta=0.5), [2.0, 1.0], [5, 4]),
                (1, dict(eta=3.0), [2.0, 1.0], [3, 6]),
@@ -389,7 +413,8 @@ UNEVEN_CFGS = [(0, dict(eta=0.5), [2.0, 1.0], [5, 4]),
                (2, dict(eta=0.25, use_jac=True), [2.0, 1.0], [4, 2]),
                (0, dict(eta=2.0, sigma_warp=0.0), [4.0, 2.0, 1.0], [2, 3, 2]),
                (1, dict(eta=0.5, window=7, sigma_grad=1.5), [2.0, 1.0], [2, 3]),
-               (2, dict(eta=1.0), [1.0], [9])]
+               (2, dict(eta=1.0), [1.0], [9]),
+               (0, dict(eta=0.25, sigma_grad=6.0, sigma_warp=0.4), [2.0, 1.0], [3, 3])]
 _UNEVEN_ORACLE = {}
 
 
