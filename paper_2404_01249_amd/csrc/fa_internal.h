@@ -49,6 +49,7 @@ constexpr int kCubeZ = 4, kCubeY = 8, kCubeX = 16;   // brick of a cube launch
 struct GradArgs {
   const float* fixed;
   const float* moving_pad;   // moving image with a zero border of kPad voxels
+  const float* moving_quad;  // the same as corner quads (launch_pad_quad), or NULL
   const float* d;        // [3][N]
   float* m;              // [3][N] (Adam mode)
   float* v;              // [3][N]
@@ -117,8 +118,9 @@ hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tili
 // Batched forms: `total` workgroups over the entries E (device memory) with
 // owner (device memory, `total` ints); t gives the template parameters only
 // (tile shape, brick or march) and must be the tiling of every entry.
+// quad: every entry's moving_quad is set (the corner-quad gathers).
 hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
-                             const Tiling& t, hipStream_t s);
+                             const Tiling& t, bool quad, hipStream_t s);
 hipError_t launch_gauss_batch(const BatchEntry<GaussArgs>* E, const int* owner, int total, int radius,
                               int epilogue, const Tiling& t, hipStream_t s);
 // Whether a batched form exists for these parameters.
@@ -132,6 +134,9 @@ hipError_t launch_eulerian_adam(float* ga, const float* d, float* m, float* v, C
 hipError_t launch_fill(float* p, float value, int64_t n, hipStream_t s);
 // out = in with a zero border of kPad voxels (padded_voxels(n0, n1, n2) floats).
 hipError_t launch_pad(const float* in, float* out, int n0, int n1, int n2, hipStream_t s);
+// Corner quads of the padded image `pad` (padded_voxels(n0, n1, n2) float4s
+// into quad, 16-byte aligned; quad_supported must hold).
+hipError_t launch_pad_quad(const float* pad, float* quad, int n0, int n1, int n2, hipStream_t s);
 hipError_t launch_blur_axis(const float* in, float* out, int n0, int n1, int n2, int axis,
                             const float* wts, int radius, hipStream_t s);
 hipError_t launch_resample(const float* in, float* out, int nin0, int nin1, int nin2,
@@ -166,6 +171,11 @@ constexpr int kMaxWindow = 9;
 constexpr int kPad = 2;
 inline int64_t padded_voxels(int n0, int n1, int n2) {
   return (int64_t)(n0 + 2 * kPad) * (n1 + 2 * kPad) * (n2 + 2 * kPad);
+}
+// Whether the corner-quad copy of a padded volume stays below 4 GiB (its
+// gathers use 32-bit byte offsets).
+inline bool quad_supported(int n0, int n1, int n2) {
+  return (uint64_t)padded_voxels(n0, n1, n2) * 16u < ((uint64_t)1 << 32);
 }
 // Gaussian radii: the streaming and brick kernels take 0..kMaxRadius as a
 // template parameter; launch_gauss runs radii up to kMaxWideRadius through

@@ -359,6 +359,42 @@ __device__ __forceinline__ void gather_issue(const float* __restrict__ f, const 
   g.t2 = c.t2;
 }
 
+// The padded moving image stored as corner quads (launch_pad_quad): entry
+// (z, y, x) of the padded grid holds the padded values at (z, y, x),
+// (z, y, x+1), (z, y+1, x) and (z, y+1, x+1).  A trilinear sample then takes
+// two aligned 16-byte loads (planes z and z+1 of its cell) instead of eight
+// 4-byte ones, and the corners arrive in gather_issue's order, so the values
+// and every result are the same.  Byte offsets are 32-bit unsigned (the quad
+// array stays below 4 GiB; the runtime checks it).
+__device__ __forceinline__ void quad_axis(int x, float dd, int n, unsigned stride_bytes, unsigned& lo, float& t) {
+  dd = clamp_med3(dd, (float)(-x - kPad), (float)(n - x));
+  const float f = floorf(dd);
+  lo = (unsigned)(x + kPad + (int)f) * stride_bytes;   // padded index in [0, n + kPad]
+  t = dd - f;
+}
+
+__device__ __forceinline__ void gather_issue_quad(const float* __restrict__ q, int n0, int n1, int n2, int z,
+                                                  int y, int x, float d0, float d1, float d2, Gather& g) {
+  const unsigned p2 = (unsigned)(n2 + 2 * kPad), p1 = (unsigned)(n1 + 2 * kPad);
+  unsigned l0, l1, l2;
+  quad_axis(z, d0, n0, p1 * p2 * 16u, l0, g.t0);
+  quad_axis(y, d1, n1, p2 * 16u, l1, g.t1);
+  quad_axis(x, d2, n2, 16u, l2, g.t2);
+  const char* b = reinterpret_cast<const char*>(q);
+  const unsigned off = l0 + l1 + l2;
+  const float4 lo = *reinterpret_cast<const float4*>(b + (size_t)off);
+  const float4 hi = *reinterpret_cast<const float4*>(b + (size_t)(off + p1 * p2 * 16u));
+  g.c[0] = lo.x;
+  g.c[1] = lo.y;
+  g.c[2] = lo.z;
+  g.c[3] = lo.w;
+  g.c[4] = hi.x;
+  g.c[5] = hi.y;
+  g.c[6] = hi.z;
+  g.c[7] = hi.w;
+  g.mask = 0xFFu;
+}
+
 __device__ __forceinline__ float gather_value(const Gather& g) {
   float v[8];
 #pragma unroll
@@ -431,7 +467,7 @@ __device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex)
   }
 }
 
-template <int W, int TY, int TX, bool PIPE>
+template <int W, int TY, int TX, bool PIPE, bool QUAD = false>
 __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   constexpr int R = W / 2;
   constexpr int NT = TY * TX;
@@ -561,8 +597,12 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   auto issue_gather = [&](int z, int k) {
     gv[k] = z >= 0 && z < n0 && cin[k];
     if (gv[k]) {
-      const Cell8 c = cell8_pad(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
-      gather_issue(A.moving_pad, c, gq[k]);
+      if constexpr (QUAD) {
+        gather_issue_quad(A.moving_quad, n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k], gq[k]);
+      } else {
+        const Cell8 c = cell8_pad(n0, n1, n2, z, cy[k], cx[k], nd0[k], nd1[k], nd2[k]);
+        gather_issue(A.moving_pad, c, gq[k]);
+      }
       nxI[k] = nf[k] - si;
     }
   };
@@ -810,9 +850,9 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
 
 // The same kernel compiled for two workgroups per CU (at most 128 VGPRs);
 // used where that fits without spilling.
-template <int W, int TY, int TX, bool PIPE>
+template <int W, int TY, int TX, bool PIPE, bool QUAD = false>
 __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4))) k_grad_o4(const GradArgs A) {
-  grad_body<W, TY, TX, PIPE>(A, xcd_tile(blockIdx.x, gridDim.x));
+  grad_body<W, TY, TX, PIPE, QUAD>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1604,6 +1644,7 @@ __device__ __forceinline__ T* as_global(T* p) {
 __device__ __forceinline__ void load_args(const GradArgs* __restrict__ s, GradArgs& A) {
   A.fixed = as_global(s->fixed);
   A.moving_pad = as_global(s->moving_pad);
+  A.moving_quad = as_global(s->moving_quad);
   A.d = as_global(s->d);
   A.m = as_global(s->m);
   A.v = as_global(s->v);
@@ -1664,13 +1705,13 @@ __global__ void __launch_bounds__(TY * TX) k_grad_batch(const BatchEntry<GradArg
   grad_body<W, TY, TX, true>(A, tile);
 }
 
-template <int W, int TY, int TX>
+template <int W, int TY, int TX, bool QUAD = false>
 __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)))
 k_grad_o4_batch(const BatchEntry<GradArgs>* __restrict__ E, const int* __restrict__ owner) {
   GradArgs A;
   int nb;
   const int tile = batch_entry(E, owner, A, nb);
-  grad_body<W, TY, TX, true>(A, tile);
+  grad_body<W, TY, TX, true, QUAD>(A, tile);
 }
 
 template <int R, int TY, int TX, int EPI>
@@ -1787,6 +1828,24 @@ __global__ void k_pad(const float* __restrict__ in, float* __restrict__ out, int
     const bool in_grid = z >= 0 && z < n0 && y >= 0 && y < n1 && x >= 0 && x < n2;
     out[i] = in_grid ? in[((int64_t)z * n1 + y) * n2 + x] : 0.0f;
   }
+}
+
+// Corner quads of the padded image (gather_issue_quad): quad[i] = (pad[i],
+// pad[i+1], pad[i+p2], pad[i+p2+1]) over the padded grid, zero where a corner
+// leaves it (the last padded row and column, never the low corner of a cell).
+__global__ void k_pad_quad(const float* __restrict__ pad, float4* __restrict__ quad, int p0, int p1, int p2) {
+  const int64_t n = (int64_t)p0 * p1 * p2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % p2);
+  const int y = (int)((i / p2) % p1);
+  const bool xo = x + 1 < p2, yo = y + 1 < p1;
+  float4 q;
+  q.x = pad[i];
+  q.y = xo ? pad[i + 1] : 0.0f;
+  q.z = yo ? pad[i + p2] : 0.0f;
+  q.w = (xo && yo) ? pad[i + p2 + 1] : 0.0f;
+  quad[i] = q;
 }
 
 __global__ void k_fill(float* __restrict__ p, float value, int64_t n) {
@@ -2078,6 +2137,7 @@ hipError_t grad_launch_t(const GradArgs& a, const Tiling& t, hipStream_t s) {
   const dim3 g(t.blocks()), blk(TY * TX);
   if constexpr (occ2) {
     if (t.variant == 2) k_grad_o4<W, TY, TX, false><<<g, blk, sh, s>>>(a);
+    else if (a.moving_quad) k_grad_o4<W, TY, TX, true, true><<<g, blk, sh, s>>>(a);
     else k_grad_o4<W, TY, TX, true><<<g, blk, sh, s>>>(a);
   } else {
     if (t.variant == 2) k_grad<W, TY, TX, false><<<g, blk, sh, s>>>(a);
@@ -2187,24 +2247,28 @@ hipError_t grad_launch_cube(const GradArgs& a, int window, const Tiling& t, hipS
 
 // ---- batched launches ------------------------------------------------------
 template <int W, int TY, int TX>
-hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int total, hipStream_t s) {
+hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int total, bool quad, hipStream_t s) {
   constexpr size_t sh = grad_lds<W, TY, TX>();
   constexpr bool occ2 = (W <= 5) && TY == 16 && TX == 32;
   const dim3 g(total), blk(TY * TX);
-  if constexpr (occ2) k_grad_o4_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
-  else k_grad_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
+  if constexpr (occ2) {
+    if (quad) k_grad_o4_batch<W, TY, TX, true><<<g, blk, sh, s>>>(E, owner);
+    else k_grad_o4_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
+  } else {
+    k_grad_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
+  }
   return hipGetLastError();
 }
 
 template <int TY, int TX>
-hipError_t grad_batch_tile(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
+hipError_t grad_batch_tile(const BatchEntry<GradArgs>* E, const int* owner, int total, int window, bool quad,
                            hipStream_t s) {
   switch (window) {
-    case 1: return grad_batch_t<1, TY, TX>(E, owner, total, s);
-    case 3: return grad_batch_t<3, TY, TX>(E, owner, total, s);
-    case 5: return grad_batch_t<5, TY, TX>(E, owner, total, s);
-    case 7: return grad_batch_t<7, TY, TX>(E, owner, total, s);
-    case 9: return grad_batch_t<9, TY, TX>(E, owner, total, s);
+    case 1: return grad_batch_t<1, TY, TX>(E, owner, total, quad, s);
+    case 3: return grad_batch_t<3, TY, TX>(E, owner, total, quad, s);
+    case 5: return grad_batch_t<5, TY, TX>(E, owner, total, quad, s);
+    case 7: return grad_batch_t<7, TY, TX>(E, owner, total, quad, s);
+    case 9: return grad_batch_t<9, TY, TX>(E, owner, total, quad, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2341,7 +2405,7 @@ bool gauss_batch_supported(int radius, int epilogue, const Tiling& t) {
 }
 
 hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
-                             const Tiling& t, hipStream_t s) {
+                             const Tiling& t, bool quad, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   if (t.cube) {
     switch (window) {
@@ -2351,8 +2415,8 @@ hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, in
       default: return hipErrorInvalidValue;
     }
   }
-  if (t.ty == 16 && t.tx == 32) return grad_batch_tile<16, 32>(E, owner, total, window, s);
-  if (t.ty == 8 && t.tx == 32) return grad_batch_tile<8, 32>(E, owner, total, window, s);
+  if (t.ty == 16 && t.tx == 32) return grad_batch_tile<16, 32>(E, owner, total, window, quad, s);
+  if (t.ty == 8 && t.tx == 32) return grad_batch_tile<8, 32>(E, owner, total, window, quad, s);
   return hipErrorInvalidValue;
 }
 
@@ -2461,6 +2525,14 @@ hipError_t blur_axis_run(const float* in, float* out, int n0, int n1, int n2, in
 template <int R>
 hipError_t blur_x(const float* in, float* out, int n0, int n1, int n2, const float* wts, hipStream_t s) {
   hipLaunchKernelGGL((k_blur_x<R>), dim3(grid1(n2, 256), n1, n0), dim3(256), 0, s, in, out, n2, wts);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_quad(const float* pad, float* quad, int n0, int n1, int n2, hipStream_t s) {
+  const int p0 = n0 + 2 * kPad, p1 = n1 + 2 * kPad, p2 = n2 + 2 * kPad;
+  const int64_t n = (int64_t)p0 * p1 * p2;
+  hipLaunchKernelGGL(k_pad_quad, dim3(grid1(n, 256)), dim3(256), 0, s, pad, reinterpret_cast<float4*>(quad), p0,
+                     p1, p2);
   return hipGetLastError();
 }
 

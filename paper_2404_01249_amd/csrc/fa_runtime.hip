@@ -91,6 +91,7 @@ struct Level {
   float* fixed = nullptr;   // owned unless it aliases the input copy
   float* moving = nullptr;
   float* moving_pad = nullptr;  // moving with a zero border (owned), sampled by the gradient kernel
+  float* moving_quad = nullptr; // the same as corner quads (owned; NULL where it would reach 4 GiB)
   bool owns = false;
   Tiling tg{}, tsg{}, tsc{}, tsw{};  // gradient, sigma_grad, composition and sigma_warp launches
   bool tuned[4] = {false, false, false, false};  // set by fa_pair_autotune (by KernelKind)
@@ -178,6 +179,7 @@ void free_levels(fa_pair P) {
       (void)hipFree(L.moving);
     }
     if (L.moving_pad) (void)hipFree(L.moving_pad);
+    if (L.moving_quad) (void)hipFree(L.moving_quad);
   }
   P->levels.clear();
 }
@@ -274,6 +276,7 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   ga = fa::GradArgs{};
   ga.fixed = fixed ? fixed : (P->fixed_override ? P->fixed_override : L.fixed);
   ga.moving_pad = L.moving_pad;
+  ga.moving_quad = L.moving_quad;
   ga.d = P->d;
   ga.m = P->m;
   ga.v = P->v;
@@ -440,6 +443,7 @@ struct BatchLaunch {
   size_t ent_off;  // byte offsets of the entries and the owner array
   size_t own_off;
   int total;       // workgroups of the launch
+  bool quad = false;   // gradient: the entries gather from corner quads
   // radius above 6: no batched form; each entry's launches run one after
   // another from these host-side arguments instead
   std::vector<fa::GaussArgs> singles;
@@ -500,7 +504,9 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
     if (taken[i]) continue;
     std::vector<size_t> mem;
     for (size_t j = i; j < n; ++j) {
-      if (taken[j] || its[j].window != its[i].window || !same_form(its[j].tg, its[i].tg)) continue;
+      if (taken[j] || its[j].window != its[i].window || !same_form(its[j].tg, its[i].tg) ||
+          (its[j].ga.moving_quad != nullptr) != (its[i].ga.moving_quad != nullptr))
+        continue;
       taken[j] = 1;
       mem.push_back(j);
     }
@@ -512,8 +518,10 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
     for (size_t j : mem) {
       ts.push_back(&its[j].tg);
       n0s.push_back(its[j].ga.n0);
-      pinned.push_back(live[j]->tune[fa::KIND_GRAD].zc > 0 ||
-                       live[j]->levels[live[j]->cur_level].tuned[fa::KIND_GRAD]);
+      // a chunk set by fa_pair_set_tuning is kept; an autotuned one is not:
+      // it was timed with the GPU to one pair, and the entries of a batched
+      // launch share the resident slots (the tuned tile shape and form stay)
+      pinned.push_back(live[j]->tune[fa::KIND_GRAD].zc > 0);
     }
     std::vector<Tiling> orig;
     for (size_t j : mem) orig.push_back(its[j].tg);
@@ -530,6 +538,7 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
       nb.push_back(its[j].tg.blocks());
     }
     append_launch(bt, 0, its[i].tg, its[i].window, 0, args, nb);
+    bt.launches.back().quad = its[i].ga.moving_quad != nullptr;
   }
   // stages 1 to 3, grouped by radius, epilogue and tiling form
   static const fa::KernelKind kinds[3] = {fa::KIND_SMOOTH_MAX, fa::KIND_COMPOSE, fa::KIND_WARP_SMOOTH};
@@ -562,7 +571,7 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
       for (size_t j : mem) {
         ts.push_back(&its[j].tgs[k]);
         n0s.push_back(its[j].g[k].n0);
-        pinned.push_back(live[j]->tune[kinds[k]].zc > 0 || live[j]->levels[live[j]->cur_level].tuned[kinds[k]]);
+        pinned.push_back(live[j]->tune[kinds[k]].zc > 0);   // as for the gradient launch
       }
       // halo planes: 2R of the smoothing, one plane ahead for the composition
       fa::batch_chunks(kinds[k], k == 1 ? 2 : 2 * its[i].radius[k], ts, n0s, pinned);
@@ -613,7 +622,7 @@ fa_status launch_batch_iteration(const std::vector<fa_pair>& live, const BatchTa
     const int* own = reinterpret_cast<const int*>(base + bl.own_off);
     if (bl.stage == 0) {
       const auto* E = reinterpret_cast<const fa::BatchEntry<fa::GradArgs>*>(base + bl.ent_off);
-      FA_HIP(fa::launch_grad_batch(E, own, bl.total, bl.param, bl.t, s));
+      FA_HIP(fa::launch_grad_batch(E, own, bl.total, bl.param, bl.t, bl.quad, s));
     } else {
       const auto* E = reinterpret_cast<const fa::BatchEntry<fa::GaussArgs>*>(base + bl.ent_off);
       FA_HIP(fa::launch_gauss_batch(E, own, bl.total, bl.param, bl.epi, bl.t, s));
@@ -1025,6 +1034,11 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
   for (auto& L : P->levels) {
     FA_TRY(dalloc(&L.moving_pad, (size_t)fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2), "padded moving"));
     FA_HIP(fa::launch_pad(L.moving, L.moving_pad, L.shape.n0, L.shape.n1, L.shape.n2, P->stream));
+    if (fa::quad_supported(L.shape.n0, L.shape.n1, L.shape.n2)) {
+      FA_TRY(dalloc(&L.moving_quad, (size_t)4 * fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2),
+                    "padded moving quads"));
+      FA_HIP(fa::launch_pad_quad(L.moving_pad, L.moving_quad, L.shape.n0, L.shape.n1, L.shape.n2, P->stream));
+    }
   }
 
   // State: phi = id, m = v = 0, t = 0.
@@ -1226,6 +1240,7 @@ fa_status fa_pair_eval_gradient(fa_pair P, float* g_dev, float* loss_host) {
   fa::GradArgs ga{};
   ga.fixed = L.fixed;
   ga.moving_pad = L.moving_pad;
+  ga.moving_quad = L.moving_quad;
   ga.d = P->d;
   ga.out = g_dev ? g_dev : P->tmp;
   ga.partials = P->partials;
