@@ -41,8 +41,11 @@ Prints one JSON line.  Besides the headline value it reports
 * ``accuracy``: Dice of the transferred tissue labels and the fraction of
   singular voxels for the fused result and the plain PyTorch result (the
   "same accuracy" condition of the comparison);
+* ``lung_ct_params``: the same registration with the paper's lung CT
+  (EMPIRE10) hyperparameters, eta 0.25, sigma_grad 6, sigma_warp 0.4;
 * ``cpu_baseline``: the FP64 NumPy oracle timed on the host, on a bounded
-  sample of the same workload.
+  sample of the same workload, on one core (with the host's core count) and
+  as independent runs in parallel processes.
 """
 import argparse
 import json
@@ -479,35 +482,57 @@ def run_batch_compare(p, k, params):
     return out
 
 
-def run_grid_search(n_variants, params, sequential_too=True):
-    """The grid-search batch: pairs of three sizes (96^3, 128x160x128,
-    160x192x224; blob volumes as in the 64^3 workload, blob widths scaled to
-    the size), each registered at four step sizes (eta 0.25, 0.5, 1, 2) over
-    scales 2, 1 at 100, 50 iterations.  One pair is generated per size; its
-    n_variants variants are the pair flipped along subsets of the axes
-    (distinct pairs with the same statistics).  Returns the seconds of the
-    registrations run one after another and as one fused batch, and the
-    voxel-iterations of the batch."""
+GRID_SIZES = [(96, 96, 96), (128, 160, 128), (160, 192, 224)]
+
+
+def _grid_pair(args):
+    """Worker: one pair of the grid-search batch (blob volume as in the 64^3
+    workload, blob widths scaled to the size), seed 400 + i."""
+    shp, seed = args
+    from paper_2404_01249_amd import synth
+    sp = synth.blobs_pair(shp, seed=seed, n_blobs=20, sigma_range=(4.0 * min(shp) / 64, 8.0 * min(shp) / 64),
+                          field_sigma=6.0, field_max=3.0)
+    return sp.fixed, sp.moving
+
+
+def grid_pairs(n_per_size, workers):
+    """The n_per_size seeded pairs of each size (seeds 400 + i, i counting
+    over all pairs), generated in a pool of worker processes."""
+    jobs = [(shp, 400 + k * n_per_size + i) for k, shp in enumerate(GRID_SIZES) for i in range(n_per_size)]
+    if workers <= 1:
+        return jobs, [_grid_pair(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return jobs, pool.map(_grid_pair, jobs)
+
+
+def run_grid_search(n_per_size, params, sequential_too=True, workers=8):
+    """The grid-search batch: n_per_size seeded pairs of each of three sizes
+    (96^3, 128x160x128, 160x192x224), each registered at four step sizes
+    (eta 0.25, 0.5, 1, 2) over scales 2, 1 at 100, 50 iterations.  Returns the
+    seconds of the registrations run one after another and as one fused batch
+    (eager, with graph replay, and with launch shapes picked by the autotuner
+    on one pair of each size), the voxel-iterations of the batch and the
+    generation time."""
     import torch
 
-    from paper_2404_01249_amd import Pair, run_batch, synth
+    from paper_2404_01249_amd import Pair, fa, run_batch
     etas = [0.25, 0.5, 1.0, 2.0]
     scales, iters = [2.0, 1.0], [100, 50]
     base = {k: v for k, v in params.items() if k != "eta"}
-    pairs, vox_iters = [], 0
-    for k, shp in enumerate([(96, 96, 96), (128, 160, 128), (160, 192, 224)]):
-        sp = synth.blobs_pair(shp, seed=400 + k, n_blobs=20, sigma_range=(4.0 * min(shp) / 64, 8.0 * min(shp) / 64),
-                              field_sigma=6.0, field_max=3.0)
-        f0 = torch.from_numpy(sp.fixed).cuda()
-        m0 = torch.from_numpy(sp.moving).cuda()
-        for v in range(n_variants):
-            axes = [a for a in range(3) if (v >> a) & 1]
-            f = torch.flip(f0, axes).contiguous() if axes else f0
-            m = torch.flip(m0, axes).contiguous() if axes else m0
-            for e in etas:
-                pairs.append(Pair(f, m, eta=e, **base))
-                vox_iters += sum(int(np.prod([int(np.floor(n / s + 0.5)) for n in shp])) * it
-                                 for s, it in zip(scales, iters))
+    g0 = time.perf_counter()
+    jobs, vols = grid_pairs(n_per_size, workers)
+    gen_s = time.perf_counter() - g0
+    pairs, vox_iters, firsts = [], 0, {}
+    for (shp, _), (fx, mv) in zip(jobs, vols):
+        f = torch.from_numpy(fx).cuda()
+        m = torch.from_numpy(mv).cuda()
+        for e in etas:
+            pairs.append(Pair(f, m, eta=e, **base))
+            firsts.setdefault(shp, pairs[-1])
+            vox_iters += sum(int(np.prod([int(np.floor(n / s + 0.5)) for n in shp])) * it
+                             for s, it in zip(scales, iters))
+    del vols
     torch.cuda.synchronize()
 
     def sequential():
@@ -528,7 +553,7 @@ def run_grid_search(n_variants, params, sequential_too=True):
         run_batch(pairs, fused=True, graphs=True)
         torch.cuda.synchronize()
 
-    out = {"registrations": len(pairs), "voxel_iters": vox_iters}
+    out = {"registrations": len(pairs), "voxel_iters": vox_iters, "generation_s": gen_s}
     forms = (("sequential", sequential), ("fused", fused), ("fused_graphs", fused_graphs)) if sequential_too \
         else (("fused", fused),)
     for name, fn in forms:
@@ -536,6 +561,19 @@ def run_grid_search(n_variants, params, sequential_too=True):
         t0 = time.perf_counter()
         fn()
         out[name] = time.perf_counter() - t0
+    # autotuned: shapes timed on one pair of each size (kept per level grid, so
+    # every pair of that size takes them; batched launches keep tuned chunks)
+    t0 = time.perf_counter()
+    for pr in firsts.values():
+        pr.set_schedule(scales, iters)
+        pr.autotune(trials=3)
+    torch.cuda.synchronize()
+    out["tuning_s"] = time.perf_counter() - t0
+    fused()
+    t0 = time.perf_counter()
+    fused()
+    out["fused_tuned"] = time.perf_counter() - t0
+    fa.fa_autotune_clear()      # the kept shapes are process-wide
     for pr in pairs:
         pr.close()
     return out
@@ -574,9 +612,48 @@ def accuracy(p, d):
             "singular_fraction": evaluate.singular_fraction(d)}
 
 
-def cpu_baseline(p, params, budget_s=20.0):
+def _oracle_iterations(args):
+    """Worker of the parallel oracle leg: n_it iterations of the FP64 oracle
+    at the finest level from the identity state (one process, one thread).
+    Returns (iterations, wall seconds, voxels)."""
+    name, params, n_it = args
+    import oracle as O
+    from paper_2404_01249_amd import synth
+    p = synth.load(name)
+    P = O.Params(eta=params["eta"], sigma_grad=params["sigma_grad"], sigma_warp=params["sigma_warp"],
+                 window=params["window"])
+    f = p.fixed.astype(np.float64)
+    mv = p.moving.astype(np.float64)
+    d = np.zeros((3,) + f.shape)
+    m = np.zeros_like(d)
+    v = np.zeros_like(d)
+    w0 = time.perf_counter()
+    for k in range(n_it):
+        d, m, v, _, _ = O.iterate(f, mv, d, m, v, k + 1, P)
+    return n_it, time.perf_counter() - w0, f.size
+
+
+def cpu_parallel(p, params, processes, n_it):
+    """P independent oracle runs at once (P processes of one thread each, as
+    independent registrations of a batch would run): aggregate
+    voxel-iterations per second over the wall time of the whole pool."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")     # the parent has initialised the GPU: no fork
+    w0 = time.perf_counter()
+    with ctx.Pool(processes) as pool:
+        res = pool.map(_oracle_iterations, [(p.name, params, n_it)] * processes)
+    wall = time.perf_counter() - w0
+    vox_its = sum(r[0] * r[2] for r in res)
+    return {"processes": processes, "cores": processes, "value": vox_its / wall, "unit": "voxel-iters/s",
+            "wall_s": wall, "per_process_s": [round(r[1], 2) for r in res],
+            "sample": f"{processes} processes x {n_it} oracle iteration(s) at the finest level, one thread each "
+                      f"(wall clock of the pool, process start and input loading included)"}
+
+
+def cpu_baseline(p, params, budget_s=20.0, processes=0):
     """The FP64 oracle on a bounded sample: iterations at the finest level
-    from the identity state until ~budget_s of CPU time is spent."""
+    from the identity state until ~budget_s of CPU time is spent; then, with
+    processes > 1, that many independent oracle runs at once."""
     import numpy as np
 
     import oracle as O
@@ -598,9 +675,17 @@ def cpu_baseline(p, params, budget_s=20.0):
     cpu = time.process_time() - t0
     wall = time.perf_counter() - w0
     rate = f.size * n_it / wall
-    return {"value": rate, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_it} iteration(s) of Algorithm 1 at the finest 160x192x224 level from the "
-                      f"identity state, FP64 NumPy, single thread ({wall:.1f} s wall, {cpu:.1f} s CPU)"}
+    out = {"value": rate, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+           "host_cores": os.cpu_count(),
+           "sample": f"{n_it} iteration(s) of Algorithm 1 at the finest 160x192x224 level from the "
+                     f"identity state, FP64 NumPy, single thread ({wall:.1f} s wall, {cpu:.1f} s CPU), "
+                     f"1 of {os.cpu_count()} host cores"}
+    if processes > 1:
+        try:
+            out["parallel"] = cpu_parallel(p, params, processes, max(1, min(2, n_it)))
+        except Exception as e:  # the parallel leg must not hide the single-core figure
+            out["parallel"] = {"error": f"{type(e).__name__}: {e}"}
+    return out
 
 
 def main():
@@ -634,6 +719,12 @@ def main():
                     help="registrations run with per-kernel HIP events after the timed ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-processes", type=int, default=16,
+                    help="independent oracle runs at once for the parallel CPU figure (<= 1 skips)")
+    ap.add_argument("--workers", type=int, default=8,
+                    help="host processes generating the grid-search pairs")
+    ap.add_argument("--lungct-steps", type=int, default=1,
+                    help="timed registrations with the paper's lung CT hyperparameters (0 skips)")
     ap.add_argument("--calib", action="store_true",
                     help="first run a 256 MiB read + 256 MiB write elementwise kernel "
                          "(reference for hardware byte counters)")
@@ -683,6 +774,10 @@ def main():
         steady = {"us_per_iteration": iter_ms_fin * 1e3, "voxel_iters_per_s": n_fin / (iter_ms_fin / 1e3),
                   "roofline_frac_80B": GRAD_BYTES_PER_VOXEL * n_fin / (iter_ms_fin / 1e3) / 1e9 / HBM_PEAK_GBS,
                   "source": "sum of the four kernels' average HIP-event times at the finest level"}
+    if steady:
+        roof["whole_iteration"] = {
+            "us": steady["us_per_iteration"], "frac_80B": steady["roofline_frac_80B"],
+            "note": "all launches of one finest-level iteration against the same 80 B/voxel algorithmic bytes"}
     if args.graph_reps > 0:
         g_us = run_steady_graph(p, params, reps=args.graph_reps)
         steady = dict(steady or {})
@@ -729,12 +824,16 @@ def main():
                         "streams_speedup": bt["sequential"] / bt["batched"],
                         "fused_speedup": bt["sequential"] / bt["fused"]}
     if args.grid > 0:
-        g = run_grid_search(min(args.grid, 8), params, not args.grid_fused_only)
+        g = run_grid_search(min(args.grid, 8), params, not args.grid_fused_only, workers=args.workers)
         out["grid_search"] = {
             "registrations": g["registrations"],
             "sizes": ["96x96x96", "128x160x128", "160x192x224"], "etas": [0.25, 0.5, 1.0, 2.0],
+            "pairs": f"{min(args.grid, 8)} seeded pairs per size (seeds 400-{400 + 3 * min(args.grid, 8) - 1})",
             "schedule": "scales [2.0, 1.0] at [100, 50]", "voxel_iters": g["voxel_iters"],
-            "fused_s": g["fused"], "fused_voxel_iters_per_s": g["voxel_iters"] / g["fused"]}
+            "generation_s": g["generation_s"],
+            "fused_s": g["fused"], "fused_voxel_iters_per_s": g["voxel_iters"] / g["fused"],
+            "fused_tuned_s": g["fused_tuned"], "fused_tuned_voxel_iters_per_s": g["voxel_iters"] / g["fused_tuned"],
+            "tuning_s": g["tuning_s"]}
         if "sequential" in g:
             out["grid_search"].update({
                 "fused_graphs_s": g["fused_graphs"],
@@ -766,6 +865,16 @@ def main():
         out["symmetric"] = {"ms_per_step": sms, "runtime_ratio": sms / ms, "final_halfway_loss": float(sloss[-1]),
                             "inverse": "scales [4.0, 2.0, 1.0] at %s, eta 0.2" % SYM_INVERSE_ITERS,
                             "accuracy": accuracy(p, sfield)}
+    if args.lungct_steps > 0:
+        lparams = dict(params, eta=0.25, sigma_grad=6.0, sigma_warp=0.4)
+        lms, _, _, _, lloss, lfield = run_fused(p, args.lungct_steps, 1, lparams, 0)
+        out["lung_ct_params"] = {
+            "hyperparameters": "eta 0.25, sigma_grad 6.0, sigma_warp 0.4 (the paper's EMPIRE10 settings; "
+                               "Gaussian radii 18 and 2)",
+            "ms_per_step": lms, "runtime_ratio": lms / ms, "voxel_iters_per_s": vox_iters / (lms / 1e3),
+            "final_loss": float(lloss[-1])}
+        if acc:
+            out["lung_ct_params"]["accuracy"] = accuracy(p, lfield)
     if args.jac_steps > 0:
         jms, jloss, jfield = run_use_jac(p, args.jac_steps, params)
         out["use_jac"] = {"ms_per_step": jms, "runtime_ratio": jms / ms, "final_loss": jloss}
@@ -790,7 +899,8 @@ def main():
         except Exception as e:  # the comparison must not hide the headline line
             out["plain_torch"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, params, args.cpu_budget)
+        procs = min(args.cpu_processes, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(p, params, args.cpu_budget, procs)
     print(json.dumps(out), flush=True)
 
 

@@ -125,3 +125,43 @@ def register(fixed, moving, scales, iters, eta=0.5, sigma_grad=1.0, sigma_warp=0
                 d = u + torch.cat([warp(d[:, c:c + 1], ident + u) for c in range(3)], 1)
                 d = smooth(d, sigma_warp)
     return d[0], torch.stack(losses).cpu().numpy() if losses else []
+
+
+if __name__ == "__main__":
+    # Standalone run for kernel traces and counters of the plain form:
+    #   python3 bench_plain.py --workload tissue160 --scales 1 --iters 3
+    import argparse
+    import os
+    import sys
+    import time
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_2404_01249_amd import synth
+
+    ap = argparse.ArgumentParser(description="plain per-op PyTorch registration (comparison baseline)")
+    ap.add_argument("--workload", default="tissue160")
+    ap.add_argument("--scales", type=float, nargs="+", default=None)
+    ap.add_argument("--iters", type=int, nargs="+", default=None)
+    ap.add_argument("--reps", type=int, default=1)
+    ap.add_argument("--calib", action="store_true",
+                    help="first run a 256 MiB read + 256 MiB write elementwise kernel "
+                         "(reference for hardware byte counters)")
+    args = ap.parse_args()
+    if args.calib:
+        x = torch.ones(64 * 1024 * 1024, device="cuda")
+        y = torch.empty_like(x)
+        torch.add(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
+    p = synth.load(args.workload)
+    scales = args.scales or p.scales
+    iters = args.iters or p.iters
+    fixed = torch.from_numpy(p.fixed).cuda()
+    moving = torch.from_numpy(p.moving).cuda()
+    for r in range(args.reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, losses = register(fixed, moving, scales, iters, window=p.window)
+        torch.cuda.synchronize()
+        print(f"plain registration {r}: scales {scales} iters {iters}: {time.perf_counter() - t0:.3f} s, "
+              f"final loss {float(losses[-1]):.6f}", flush=True)
