@@ -1182,7 +1182,7 @@ struct GradCubeShape {
   static constexpr size_t lds_bytes = sizeof(float) * (size_t)(SA + SB);
 };
 
-template <int W, int TZ, int TY, int TX>
+template <int W, int TZ, int TY, int TX, bool QUAD = false>
 __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile) {
   using S = GradCubeShape<W, TZ, TY, TX>;
   constexpr int R = S::R;
@@ -1217,10 +1217,15 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
   float oI = 0.f, oJ = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   float pm[3] = {0.f, 0.f, 0.f}, pv[3] = {0.f, 0.f, 0.f};
   if (own) {
-    const Cell8 c = cell8_pad(n0, n1, n2, oz, oy, ox, load_at(A.d, ooff), load_at(A.d + N, ooff),
-                              load_at(A.d + 2 * N, ooff));
     Gather gq;
-    gather_issue(A.moving_pad, c, gq);
+    if constexpr (QUAD) {
+      gather_issue_quad(A.moving_quad, n0, n1, n2, oz, oy, ox, load_at(A.d, ooff), load_at(A.d + N, ooff),
+                        load_at(A.d + 2 * N, ooff), gq);
+    } else {
+      const Cell8 c = cell8_pad(n0, n1, n2, oz, oy, ox, load_at(A.d, ooff), load_at(A.d + N, ooff),
+                                load_at(A.d + 2 * N, ooff));
+      gather_issue(A.moving_pad, c, gq);
+    }
     oI = load_at(A.fixed, ooff) - si;
     if (A.mode == 0) {
 #pragma unroll
@@ -1261,9 +1266,14 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
       const int c = tid + (k0 + j) * NT;
       const int qz = c / (QY * QX), r = c - qz * (QY * QX);
       const int qy = r / QX, qx = r - qy * QX;
-      const Cell8 c8 = cell8_pad(n0, n1, n2, z0 - 2 * R + qz, y0 - 2 * R + qy, x0 - 2 * R + qx,
-                                 qd0[j], qd1[j], qd2[j]);
-      gather_issue(A.moving_pad, c8, gq[j]);
+      if constexpr (QUAD) {
+        gather_issue_quad(A.moving_quad, n0, n1, n2, z0 - 2 * R + qz, y0 - 2 * R + qy, x0 - 2 * R + qx, qd0[j],
+                          qd1[j], qd2[j], gq[j]);
+      } else {
+        const Cell8 c8 = cell8_pad(n0, n1, n2, z0 - 2 * R + qz, y0 - 2 * R + qy, x0 - 2 * R + qx,
+                                   qd0[j], qd1[j], qd2[j]);
+        gather_issue(A.moving_pad, c8, gq[j]);
+      }
     }
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
@@ -1728,18 +1738,18 @@ __global__ void __launch_bounds__(TY * TX) k_gauss_batch(const BatchEntry<GaussA
   gauss_body<R, TY, TX, EPI>(A, tile, nb);
 }
 
-template <int W, int TZ, int TY, int TX>
+template <int W, int TZ, int TY, int TX, bool QUAD = false>
 __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
-  grad_cube_body<W, TZ, TY, TX>(A, xcd_tile(blockIdx.x, gridDim.x));
+  grad_cube_body<W, TZ, TY, TX, QUAD>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-template <int W, int TZ, int TY, int TX>
+template <int W, int TZ, int TY, int TX, bool QUAD = false>
 __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube_batch(const BatchEntry<GradArgs>* __restrict__ E,
                                                                   const int* __restrict__ owner) {
   GradArgs A;
   int nb;
   const int tile = batch_entry(E, owner, A, nb);
-  grad_cube_body<W, TZ, TY, TX>(A, tile);
+  grad_cube_body<W, TZ, TY, TX, QUAD>(A, tile);
 }
 
 template <int R, int TZ, int TY, int TX, int EPI>
@@ -2220,20 +2230,25 @@ hipError_t gauss_launch_cube(const GaussArgs& a, int radius, int epi, const Tili
   }
 }
 
-template <int W>
-hipError_t grad_cube_w(const GradArgs& a, const Tiling& t, hipStream_t s) {
+template <int W, bool QUAD>
+hipError_t grad_cube_wq(const GradArgs& a, const Tiling& t, hipStream_t s) {
   constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
   constexpr size_t sh = GradCubeShape<W, TZ, TY, TX>::lds_bytes;
   static_assert(sh <= 160 * 1024 - 1024, "brick gradient LDS exceeds the 160 KiB of a CU");
   static bool attr_set = false;   // raise the dynamic LDS limit once per process
   if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube<W, TZ, TY, TX>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube<W, TZ, TY, TX, QUAD>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  k_grad_cube<W, TZ, TY, TX><<<dim3(t.blocks()), dim3(TZ * TY * TX), sh, s>>>(a);
+  k_grad_cube<W, TZ, TY, TX, QUAD><<<dim3(t.blocks()), dim3(TZ * TY * TX), sh, s>>>(a);
   return hipGetLastError();
+}
+
+template <int W>
+hipError_t grad_cube_w(const GradArgs& a, const Tiling& t, hipStream_t s) {
+  return a.moving_quad ? grad_cube_wq<W, true>(a, t, s) : grad_cube_wq<W, false>(a, t, s);
 }
 
 hipError_t grad_launch_cube(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
@@ -2273,19 +2288,26 @@ hipError_t grad_batch_tile(const BatchEntry<GradArgs>* E, const int* owner, int 
   }
 }
 
-template <int W>
-hipError_t grad_cube_batch_w(const BatchEntry<GradArgs>* E, const int* owner, int total, hipStream_t s) {
+template <int W, bool QUAD>
+hipError_t grad_cube_batch_wq(const BatchEntry<GradArgs>* E, const int* owner, int total, hipStream_t s) {
   constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
   constexpr size_t sh = GradCubeShape<W, TZ, TY, TX>::lds_bytes;
   static bool attr_set = false;   // raise the dynamic LDS limit once per process
   if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube_batch<W, TZ, TY, TX>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_grad_cube_batch<W, TZ, TY, TX, QUAD>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  k_grad_cube_batch<W, TZ, TY, TX><<<dim3(total), dim3(TZ * TY * TX), sh, s>>>(E, owner);
+  k_grad_cube_batch<W, TZ, TY, TX, QUAD><<<dim3(total), dim3(TZ * TY * TX), sh, s>>>(E, owner);
   return hipGetLastError();
+}
+
+template <int W>
+hipError_t grad_cube_batch_w(const BatchEntry<GradArgs>* E, const int* owner, int total, bool quad,
+                             hipStream_t s) {
+  return quad ? grad_cube_batch_wq<W, true>(E, owner, total, s) : grad_cube_batch_wq<W, false>(E, owner, total, s);
 }
 
 template <int R, int TY, int TX>
@@ -2409,9 +2431,9 @@ hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, in
   if (total <= 0) return hipSuccess;
   if (t.cube) {
     switch (window) {
-      case 1: return grad_cube_batch_w<1>(E, owner, total, s);
-      case 3: return grad_cube_batch_w<3>(E, owner, total, s);
-      case 5: return grad_cube_batch_w<5>(E, owner, total, s);
+      case 1: return grad_cube_batch_w<1>(E, owner, total, quad, s);
+      case 3: return grad_cube_batch_w<3>(E, owner, total, quad, s);
+      case 5: return grad_cube_batch_w<5>(E, owner, total, quad, s);
       default: return hipErrorInvalidValue;
     }
   }
