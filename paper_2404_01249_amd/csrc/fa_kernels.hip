@@ -902,6 +902,11 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   constexpr int XS = EY * TX;
   constexpr int CPT = (E + NT - 1) / NT;
   constexpr int DY = TY + 2, DX = TX + 2, DE = DY * DX;  // staged d planes (EPI_COMPOSE_LDS)
+  // stride of the staged planes and components: DE rounded up to a multiple
+  // of the 32 LDS banks, so that lanes of one row whose samples fall in
+  // different planes (the sign of u0 flips along the row) read different
+  // banks for different columns
+  constexpr int DEP = (DE + 31) / 32 * 32;
   constexpr int CPTD = (DE + NT - 1) / NT;
   // the x pass gives each thread two neighbouring outputs (pair reads along
   // rows): EX, E, XS and every row offset are even
@@ -909,7 +914,7 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   extern __shared__ __attribute__((aligned(16))) float glds[];
   float* buf = glds;           // [3][E]
   float* bufx = glds + 3 * E;  // [3][XS]
-  float* dring = glds + 3 * E + 3 * XS;  // [3 planes][3][DE] (EPI_COMPOSE_LDS)
+  float* dring = glds + 3 * E + 3 * XS;  // [3 planes][3][DEP] (EPI_COMPOSE_LDS)
   __shared__ double red[NT / 64];
   __shared__ int is_last;
 
@@ -992,9 +997,9 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
     for (int k = 0; k < CPTD; ++k) {
       const int c = tid + k * NT;
       if (c < DE) {
-        dring[(slot * 3 + 0) * DE + c] = pd[k][0];
-        dring[(slot * 3 + 1) * DE + c] = pd[k][1];
-        dring[(slot * 3 + 2) * DE + c] = pd[k][2];
+        dring[(slot * 3 + 0) * DEP + c] = pd[k][0];
+        dring[(slot * 3 + 1) * DEP + c] = pd[k][1];
+        dring[(slot * 3 + 2) * DEP + c] = pd[k][2];
       }
     }
   };
@@ -1122,8 +1127,8 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
         float res[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const float* pa = dring + (sA * 3 + q) * DE + cb;
-          const float* pb = dring + (sB * 3 + q) * DE + cb;
+          const float* pa = dring + (sA * 3 + q) * DEP + cb;
+          const float* pb = dring + (sB * 3 + q) * DEP + cb;
           const float e00 = pa[0] + t2 * (pa[1] - pa[0]);
           const float e01 = pa[DX] + t2 * (pa[DX + 1] - pa[DX]);
           const float e10 = pb[0] + t2 * (pb[1] - pb[0]);
@@ -2135,7 +2140,7 @@ constexpr size_t grad_lds() {
 template <int R, int TY, int TX>
 constexpr size_t gauss_lds(bool staged_d) {
   return sizeof(float) * (3 * (TY + 2 * R) * (TX + 2 * R) + 3 * (TY + 2 * R) * TX +
-                          (staged_d ? 9 * (TY + 2) * (TX + 2) : 0));
+                          (staged_d ? 9 * (((TY + 2) * (TX + 2) + 31) / 32 * 32) : 0));
 }
 
 template <int W, int TY, int TX>
@@ -2404,7 +2409,7 @@ size_t grad_lds_bytes(int window, int ty, int tx) {
 
 size_t gauss_lds_bytes(int radius, int ty, int tx) {
   return sizeof(float) * (size_t)(3 * (ty + 2 * radius) * (tx + 2 * radius) + 3 * (ty + 2 * radius) * tx +
-                                  9 * (ty + 2) * (tx + 2));
+                                  9 * (((ty + 2) * (tx + 2) + 31) / 32 * 32));
 }
 
 hipError_t launch_grad(const GradArgs& a, int window, const Tiling& t, hipStream_t s) {
