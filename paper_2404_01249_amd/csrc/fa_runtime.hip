@@ -139,6 +139,7 @@ struct fa_pair_s {
   double* scratch = nullptr;  // kMeanBlocks + 1 doubles
   float* wts = nullptr;       // device tap tables
   std::vector<float> wts_host;
+  std::vector<float> wts_dev;  // the table last copied to wts (empty: none)
   int rg = 0, rw = 0;         // Gaussian radii (sigma_grad, sigma_warp)
   int off_g = 0, off_w = 0;   // offsets of their taps in wts
   int off_one = 0;            // the single tap 1 (pointwise launches)
@@ -953,9 +954,30 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
   }
   if (total_iters > (int64_t)1 << 30) return fail(FA_EINVAL, "too many iterations");
 
-  // Release a previous schedule's pyramid and history.
-  (void)hipStreamSynchronize(P->stream);
-  free_levels(P);
+  // A previous schedule with the same level grids keeps its pyramid buffers
+  // (its images are rebuilt below all the same), and nothing waits: the new
+  // schedule's work queues behind the old one's on the stream.  Otherwise the
+  // old pyramid is released first, which waits for the work still using it.
+  bool reuse = P->levels.size() == (size_t)n_levels;
+  for (int i = 0; reuse && i < n_levels; ++i) {
+    const Level& o = P->levels[i];
+    reuse = o.scale == lv[i].scale && o.shape.n0 == lv[i].shape.n0 && o.shape.n1 == lv[i].shape.n1 &&
+            o.shape.n2 == lv[i].shape.n2;
+  }
+  if (reuse) {
+    for (int i = 0; i < n_levels; ++i) {
+      const Level& o = P->levels[i];
+      lv[i].fixed = o.fixed;
+      lv[i].moving = o.moving;
+      lv[i].owns = o.owns;
+      lv[i].moving_pad = o.moving_pad;
+      lv[i].moving_quad = o.moving_quad;
+    }
+    P->levels = lv;   // owned by the pair while the rest of the call may fail
+  } else {
+    (void)hipStreamSynchronize(P->stream);
+    free_levels(P);
+  }
   P->scheduled = false;
 
   // Tap tables: sigma_grad, sigma_warp, then one per level for the blur.
@@ -971,14 +993,25 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
   P->off_one = push(std::vector<float>{1.0f});
   P->off_blur.assign(n_levels, 0);
   for (int i = 0; i < n_levels; ++i) P->off_blur[i] = push(gaussian_taps(lv[i].scale / 2.0f));
-  if (P->wts) (void)hipFree(P->wts);
-  P->wts = nullptr;
-  FA_TRY(dalloc(&P->wts, P->wts_host.size(), "tap tables"));
-  FA_HIP(hipMemcpyAsync(P->wts, P->wts_host.data(), P->wts_host.size() * sizeof(float),
-                        hipMemcpyHostToDevice, P->stream));
+  if (!P->wts || P->wts_dev != P->wts_host) {
+    if (P->wts && P->wts_dev.size() < P->wts_host.size()) {
+      (void)hipStreamSynchronize(P->stream);
+      (void)hipFree(P->wts);
+      P->wts = nullptr;
+    }
+    if (!P->wts) {
+      P->wts_dev.clear();
+      FA_TRY(dalloc(&P->wts, std::max(P->wts_host.size(), (size_t)256), "tap tables"));
+    }
+    // stream-ordered: queued kernels still read the previous table
+    FA_HIP(hipMemcpyAsync(P->wts, P->wts_host.data(), P->wts_host.size() * sizeof(float),
+                          hipMemcpyHostToDevice, P->stream));
+    P->wts_dev = P->wts_host;
+  }
 
   const bool wide = P->rg > fa::kMaxRadius || P->rw > fa::kMaxRadius;
   if (nmax > P->cap || (wide && !P->wide)) {
+    (void)hipStreamSynchronize(P->stream);
     float** bufs[] = {&P->d, &P->m, &P->v, &P->a, &P->tmp, &P->wide};
     for (float** b : bufs) {
       if (*b) (void)hipFree(*b);
@@ -990,6 +1023,7 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     P->cap = nmax;
   }
   if (total_iters > P->loss_cap) {
+    (void)hipStreamSynchronize(P->stream);
     if (P->loss_hist) (void)hipFree(P->loss_hist);
     P->loss_hist = nullptr;
     P->loss_cap = 0;
@@ -997,6 +1031,7 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     P->loss_cap = (int)total_iters;
   }
   if (pmax > P->partials_cap) {
+    (void)hipStreamSynchronize(P->stream);
     if (P->partials) (void)hipFree(P->partials);
     P->partials = nullptr;
     P->partials_cap = 0;
@@ -1020,23 +1055,28 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
       L.owns = false;
       continue;
     }
-    fa_status st;
-    if ((st = dalloc(&L.fixed, (size_t)L.n, "pyramid")) != FA_OK) return st;
-    if ((st = dalloc(&L.moving, (size_t)L.n, "pyramid")) != FA_OK) {
-      (void)hipFree(L.fixed);
-      L.fixed = nullptr;
-      return st;
+    if (!L.fixed) {
+      fa_status st;
+      if ((st = dalloc(&L.fixed, (size_t)L.n, "pyramid")) != FA_OK) return st;
+      if ((st = dalloc(&L.moving, (size_t)L.n, "pyramid")) != FA_OK) {
+        (void)hipFree(L.fixed);
+        L.fixed = nullptr;
+        return st;
+      }
+      L.owns = true;
     }
-    L.owns = true;
     FA_TRY(build_level_image(P, P->in_fixed, L.fixed, L, P->off_blur[i]));
     FA_TRY(build_level_image(P, P->in_moving, L.moving, L, P->off_blur[i]));
   }
   for (auto& L : P->levels) {
-    FA_TRY(dalloc(&L.moving_pad, (size_t)fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2), "padded moving"));
+    if (!L.moving_pad)
+      FA_TRY(dalloc(&L.moving_pad, (size_t)fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2),
+                    "padded moving"));
     FA_HIP(fa::launch_pad(L.moving, L.moving_pad, L.shape.n0, L.shape.n1, L.shape.n2, P->stream));
     if (fa::quad_supported(L.shape.n0, L.shape.n1, L.shape.n2)) {
-      FA_TRY(dalloc(&L.moving_quad, (size_t)4 * fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2),
-                    "padded moving quads"));
+      if (!L.moving_quad)
+        FA_TRY(dalloc(&L.moving_quad, (size_t)4 * fa::padded_voxels(L.shape.n0, L.shape.n1, L.shape.n2),
+                      "padded moving quads"));
       FA_HIP(fa::launch_pad_quad(L.moving_pad, L.moving_quad, L.shape.n0, L.shape.n1, L.shape.n2, P->stream));
     }
   }
