@@ -94,11 +94,13 @@ fa_status fa_pair_create(const float* fixed_dev, const float* moving_dev, fa_sha
  * sigma = s_l/2 (none at s_l = 1) and resampled trilinearly at corner-aligned
  * positions (Section 4.5).  scales and iters are host arrays of n_levels
  * entries; scales >= 1; iters >= 0; every level dimension >= 2.
- * May be called again to restart.  Not enqueued like the other calls: it
- * synchronises the pair's stream (a previous schedule's pyramid is released
- * first) and allocates device memory with hipMalloc where the new schedule
- * needs more than the pair holds; the pyramid build and the state reset are
- * then enqueued on the stream. */
+ * May be called again to restart.  The pyramid build and the state reset are
+ * enqueued on the stream.  When the level grids differ from the previous
+ * schedule's (or on the first call), the call also synchronises the pair's
+ * stream (the previous pyramid is released first) and allocates device memory
+ * with hipMalloc; it does the same when the new schedule needs larger state,
+ * history or tap-table buffers than the pair holds.  A schedule with the same
+ * level grids reuses every buffer and returns without waiting. */
 fa_status fa_pair_set_schedule(fa_pair pair, int n_levels, const float* scales, const int* iters);
 
 /* Run up to max_iters iterations of Algorithm 1 (crossing level boundaries
