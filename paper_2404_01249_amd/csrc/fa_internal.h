@@ -94,9 +94,8 @@ struct GaussArgs {
   int n0, n1, n2;
   int zc, tiles_y, tiles_x;
   // radius above kMaxRadius only (launch_gauss): a [3][N] scratch field
-  // distinct from in and out, and the device tap table {1}
+  // distinct from in and out
   float* wide_tmp;
-  const float* one_tap;
 };
 
 // ---- batched launches ----------------------------------------------------

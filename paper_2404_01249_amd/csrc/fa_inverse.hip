@@ -461,7 +461,6 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g1.out = H->tmp;
   g1.wts = H->wts + H->off_g;
   g1.wide_tmp = H->wide;
-  g1.one_tap = H->wts + H->off_one;
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
@@ -482,7 +481,6 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g3.out = H->e;
   g3.wts = H->wts + H->off_w;
   g3.wide_tmp = H->wide;
-  g3.one_tap = H->wts + H->off_one;
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;

@@ -1904,12 +1904,18 @@ __global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ 
 // Along n1 (axis 1) or n0 (axis 0): a workgroup of 64 x 4 threads takes 64
 // consecutive n2 columns and kWideRun consecutive positions along the axis
 // (grid: ceil(n2/64), ceil(n_axis/kWideRun), the remaining axis); thread
-// (lane, j) forms the outputs j, j + 4, ... of its column.
+// (lane, j) forms the outputs j, j + 4, ... of its column.  The last pass
+// (axis 0) also runs the smoothing's epilogue (EPI): the max norm M of the
+// result (EPI_SMOOTH_MAX) or the loss record and step count (EPI_STORE_FINAL),
+// as the streaming kernels do; E carries the control block and loss fields.
 constexpr int kWideRun = 32;
-template <int AX>
+template <int AX, int EPI>
 __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
-                                                       int n0, int n1, int n2, const float* __restrict__ w, int R) {
+                                                       int n0, int n1, int n2, const float* __restrict__ w, int R,
+                                                       const GaussArgs E) {
   extern __shared__ float wl[];   // [3][kWideRun + 2R][64]
+  __shared__ double red[4];
+  __shared__ int is_last;
   const int L = kWideRun + 2 * R;
   const int lane = threadIdx.x & 63, j0 = threadIdx.x >> 6;
   const int x = blockIdx.x * 64 + lane;
@@ -1926,15 +1932,26 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
       wl[(c * L + i) * 64 + lane] = xin ? in[c * N + base + aa * astride + x] : 0.0f;
     }
   __syncthreads();
-  if (!xin) return;
-  for (int j = j0; j < kWideRun && a0 + j < na; j += 4) {
-    for (int c = 0; c < 3; ++c) {
-      const float* src = wl + (c * L + j) * 64 + lane;
-      float acc = w[0] * src[0];
-      for (int k = 1; k <= 2 * R; ++k) acc += w[k] * src[k * 64];
-      out[c * N + base + (int64_t)(a0 + j) * astride + x] = acc;
+  float mx = 0.0f;
+  if (xin) {
+    for (int j = j0; j < kWideRun && a0 + j < na; j += 4) {
+      float v[3];
+      for (int c = 0; c < 3; ++c) {
+        const float* src = wl + (c * L + j) * 64 + lane;
+        float acc = w[0] * src[0];
+        for (int k = 1; k <= 2 * R; ++k) acc += w[k] * src[k * 64];
+        v[c] = acc;
+        out[c * N + base + (int64_t)(a0 + j) * astride + x] = acc;
+      }
+      if (EPI == EPI_SMOOTH_MAX) mx = fmaxf(mx, sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
     }
   }
+  if (EPI == EPI_SMOOTH_MAX) {
+    const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
+    if (threadIdx.x == 0) atomicMax(&E.ctl->mbits, __float_as_uint(bm));
+  }
+  if (EPI == EPI_STORE_FINAL)
+    finish_iteration<256>(E, red, &is_last, (int)(gridDim.x * gridDim.y * gridDim.z));
 }
 
 __global__ void k_blur_axis(const float* __restrict__ in, float* __restrict__ out, int n0, int n1,
@@ -2466,13 +2483,12 @@ hipError_t launch_gauss_narrow(const GaussArgs& a, int radius, int epilogue, con
 }
 
 // Radius above kMaxRadius (sigma_grad or sigma_warp or the inverse's widths
-// above 2 voxels): three separable passes through a.wide_tmp, then the
-// single-tap launch of the epilogue (max norm, or loss record and step
-// count) from the smoothed field:
-//   in -> wide_tmp (n2), wide_tmp -> out (n1), out -> wide_tmp (n0),
-//   wide_tmp -> out with the epilogue.
+// above 2 voxels): three separable passes, the last with the epilogue (max
+// norm, or loss record and step count):
+//   in -> out (n2), out -> wide_tmp (n1), wide_tmp -> out (n0).
 // Needs a.wide_tmp distinct from a.in and a.out, and a.in != a.out.
 hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
+  (void)t;
   if (radius > kMaxWideRadius || !a.wide_tmp || a.wide_tmp == a.in || a.wide_tmp == a.out || a.in == a.out ||
       (epilogue != EPI_SMOOTH_MAX && epilogue != EPI_STORE_FINAL && epilogue != EPI_STORE))
     return hipErrorInvalidValue;
@@ -2480,32 +2496,22 @@ hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const
   if (n0 > 65535 || n1 > 65535) return hipErrorInvalidValue;
   const size_t shx = sizeof(float) * 3 * (256 + 2 * radius);
   const size_t shyz = sizeof(float) * 3 * (kWideRun + 2 * radius) * 64;
-  k_field_wide_x<<<dim3((n2 + 255) / 256, n1, n0), dim3(256), shx, s>>>(a.in, a.wide_tmp, n0, n1, n2, a.wts,
-                                                                         radius);
-  k_field_wide_yz<1><<<dim3((n2 + 63) / 64, (n1 + kWideRun - 1) / kWideRun, n0), dim3(256), shyz, s>>>(
-      a.wide_tmp, a.out, n0, n1, n2, a.wts, radius);
-  k_field_wide_yz<0><<<dim3((n2 + 63) / 64, (n0 + kWideRun - 1) / kWideRun, n1), dim3(256), shyz, s>>>(
-      a.out, a.wide_tmp, n0, n1, n2, a.wts, radius);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  GaussArgs b = a;
-  b.in = a.wide_tmp;
-  b.wts = a.one_tap;
-  // the epilogue launch runs the march with a single tap (any march tiling fits it)
-  Tiling tm = t;
-  if (tm.cube) tm = Tiling{};
-  if (tm.tx == 0) {
-    tm.ty = n1 >= 16 ? 16 : 8;
-    tm.tx = 32;
-    tm.tiles_y = (n1 + tm.ty - 1) / tm.ty;
-    tm.tiles_x = (n2 + tm.tx - 1) / tm.tx;
-    tm.zc = std::max(1, std::min(n0, (int)(((int64_t)n0 * tm.tiles_y * tm.tiles_x + 1023) / 1024)));
-    tm.chunks = (n0 + tm.zc - 1) / tm.zc;
+  k_field_wide_x<<<dim3((n2 + 255) / 256, n1, n0), dim3(256), shx, s>>>(a.in, a.out, n0, n1, n2, a.wts, radius);
+  k_field_wide_yz<1, EPI_STORE><<<dim3((n2 + 63) / 64, (n1 + kWideRun - 1) / kWideRun, n0), dim3(256), shyz, s>>>(
+      a.out, a.wide_tmp, n0, n1, n2, a.wts, radius, a);
+  const dim3 g0((n2 + 63) / 64, (n0 + kWideRun - 1) / kWideRun, n1);
+  switch (epilogue) {
+    case EPI_SMOOTH_MAX:
+      k_field_wide_yz<0, EPI_SMOOTH_MAX><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
+      break;
+    case EPI_STORE_FINAL:
+      k_field_wide_yz<0, EPI_STORE_FINAL><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
+      break;
+    default:
+      k_field_wide_yz<0, EPI_STORE><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
+      break;
   }
-  b.zc = tm.zc;
-  b.tiles_y = tm.tiles_y;
-  b.tiles_x = tm.tiles_x;
-  return launch_gauss_narrow(b, 0, epilogue, tm, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {

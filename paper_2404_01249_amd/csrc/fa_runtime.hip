@@ -315,7 +315,6 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g1.out = P->tmp;
   g1.wts = P->wts + P->off_g;
   g1.wide_tmp = P->wide;
-  g1.one_tap = P->wts + P->off_one;
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
@@ -346,7 +345,6 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g3.out = P->d;
   g3.wts = P->wts + P->off_w;
   g3.wide_tmp = P->wide;
-  g3.one_tap = P->wts + P->off_one;
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;
