@@ -1904,19 +1904,24 @@ __global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ 
 // Along n1 (axis 1) or n0 (axis 0): a workgroup of 64 x 4 threads takes 64
 // consecutive n2 columns and kWideRun consecutive positions along the axis
 // (grid: ceil(n2/64), ceil(n_axis/kWideRun), the remaining axis); thread
-// (lane, j) forms the outputs j, j + 4, ... of its column.  The last pass
-// (axis 0) also runs the smoothing's epilogue (EPI): the max norm M of the
-// result (EPI_SMOOTH_MAX) or the loss record and step count (EPI_STORE_FINAL),
-// as the streaming kernels do; E carries the control block and loss fields.
+// (lane, j) forms the 8 consecutive outputs 8j .. 8j+7 of its column from a
+// sliding window of 8 registers: taps go in blocks of 8 (the tap tables are
+// zero-padded to a multiple of 16, so the block past 2R + 1 adds exact
+// zeros), and each staged input is read from LDS once per thread instead of
+// once per tap.  One component is staged at a time.  The last pass (axis 0)
+// also runs the smoothing's epilogue (EPI): the max norm M of the result
+// (EPI_SMOOTH_MAX) or the loss record and step count (EPI_STORE_FINAL), as
+// the streaming kernels do; E carries the control block and loss fields.
 constexpr int kWideRun = 32;
 template <int AX, int EPI>
 __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
                                                        int n0, int n1, int n2, const float* __restrict__ w, int R,
                                                        const GaussArgs E) {
-  extern __shared__ float wl[];   // [3][kWideRun + 2R][64]
+  extern __shared__ float wl[];   // [kWideRun + L8][64], one component at a time
   __shared__ double red[4];
   __shared__ int is_last;
-  const int L = kWideRun + 2 * R;
+  const int L8 = (2 * R + 1 + 7) / 8 * 8;
+  const int LS = kWideRun + L8;
   const int lane = threadIdx.x & 63, j0 = threadIdx.x >> 6;
   const int x = blockIdx.x * 64 + lane;
   const int a0 = blockIdx.y * kWideRun;
@@ -1926,25 +1931,41 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   const int64_t astride = AX == 0 ? (int64_t)n1 * n2 : (int64_t)n2;
   const int64_t base = AX == 0 ? (int64_t)other * n2 : (int64_t)other * n1 * n2;
   const bool xin = x < n2;
-  for (int c = 0; c < 3; ++c)
-    for (int i = j0; i < L; i += 4) {
+  const int bo = 8 * j0;          // this thread's outputs, relative to a0
+  float v[3][8];
+  for (int c = 0; c < 3; ++c) {
+    if (c > 0) __syncthreads();   // the previous component's reads are done
+    for (int i = j0; i < LS; i += 4) {
       const int aa = min(max(a0 - R + i, 0), na - 1);
-      wl[(c * L + i) * 64 + lane] = xin ? in[c * N + base + aa * astride + x] : 0.0f;
+      wl[i * 64 + lane] = xin ? in[c * N + base + aa * astride + x] : 0.0f;
     }
-  __syncthreads();
-  float mx = 0.0f;
-  if (xin) {
-    for (int j = j0; j < kWideRun && a0 + j < na; j += 4) {
-      float v[3];
-      for (int c = 0; c < 3; ++c) {
-        const float* src = wl + (c * L + j) * 64 + lane;
-        float acc = w[0] * src[0];
-        for (int k = 1; k <= 2 * R; ++k) acc += w[k] * src[k * 64];
-        v[c] = acc;
-        out[c * N + base + (int64_t)(a0 + j) * astride + x] = acc;
+    __syncthreads();
+    float acc[8], xr[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      acc[o] = 0.0f;
+      xr[o] = wl[(bo + o) * 64 + lane];
+    }
+    for (int k = 0; k < L8; k += 8) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const float wk = w[k + m];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) acc[o] += wk * xr[(m + o) & 7];
+        xr[m] = wl[(bo + k + m + 8) * 64 + lane];
       }
-      if (EPI == EPI_SMOOTH_MAX) mx = fmaxf(mx, sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
     }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      v[c][o] = acc[o];
+      if (xin && a0 + bo + o < na) out[c * N + base + (int64_t)(a0 + bo + o) * astride + x] = acc[o];
+    }
+  }
+  float mx = 0.0f;
+  if (EPI == EPI_SMOOTH_MAX && xin) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+      if (a0 + bo + o < na) mx = fmaxf(mx, sqrtf(v[0][o] * v[0][o] + v[1][o] * v[1][o] + v[2][o] * v[2][o]));
   }
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
@@ -2486,7 +2507,9 @@ hipError_t launch_gauss_narrow(const GaussArgs& a, int radius, int epilogue, con
 // above 2 voxels): three separable passes, the last with the epilogue (max
 // norm, or loss record and step count):
 //   in -> out (n2), out -> wide_tmp (n1), wide_tmp -> out (n0).
-// Needs a.wide_tmp distinct from a.in and a.out, and a.in != a.out.
+// Needs a.wide_tmp distinct from a.in and a.out, a.in != a.out, and a tap
+// table a.wts of 2R + 1 taps followed by zeros up to a multiple of 16 (the
+// runtime's tables are laid out so).
 hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
   (void)t;
   if (radius > kMaxWideRadius || !a.wide_tmp || a.wide_tmp == a.in || a.wide_tmp == a.out || a.in == a.out ||
@@ -2494,8 +2517,10 @@ hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const
     return hipErrorInvalidValue;
   const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
   if (n0 > 65535 || n1 > 65535) return hipErrorInvalidValue;
+  const int l8 = (2 * radius + 1 + 7) / 8 * 8;
   const size_t shx = sizeof(float) * 3 * (256 + 2 * radius);
-  const size_t shyz = sizeof(float) * 3 * (kWideRun + 2 * radius) * 64;
+  // one component staged at a time: the run plus the taps rounded up to 8
+  const size_t shyz = sizeof(float) * (kWideRun + l8) * 64;
   k_field_wide_x<<<dim3((n2 + 255) / 256, n1, n0), dim3(256), shx, s>>>(a.in, a.out, n0, n1, n2, a.wts, radius);
   k_field_wide_yz<1, EPI_STORE><<<dim3((n2 + 63) / 64, (n1 + kWideRun - 1) / kWideRun, n0), dim3(256), shyz, s>>>(
       a.out, a.wide_tmp, n0, n1, n2, a.wts, radius, a);
