@@ -21,14 +21,15 @@ __device__ __forceinline__ float clamp_med3(float v, float lo, float hi) {
 struct Ctl {
   int t;                 // Adam step count of the iteration in flight (1-based)
   int iter;              // schedule iterations completed (index of the next loss)
-  float bc1, bc2;        // 1 - beta1^t, 1 - beta2^t (computed in double)
+  float bc1, bc2;        // 1 - beta1^t, 1 - beta2^t (from bp1, bp2)
   unsigned int mbits;    // bit pattern of M = max |s| (non-negative float)
-  unsigned int ticket;   // completion counter for the last-workgroup epilogue
   float beta1, beta2;    // copies of the Adam constants for the t update
   float shift_i, shift_j;  // mean intensities of the fixed and moving inputs; LNCC
                            // is invariant to a global intensity shift, and
                            // removing the mean reduces fp32 cancellation in the
                            // window variances
+  double bp1, bp2;       // beta1^t, beta2^t in double: pow at a level's start,
+                         // then one product per iteration
 };
 
 // Tile geometry of one streaming launch: in-plane tile (TY x TX) along
@@ -74,7 +75,6 @@ enum GaussEpilogue {
   EPI_STORE = 0,
   EPI_MAXNORM = 1,
   EPI_COMPOSE = 2,
-  EPI_STORE_FINAL = 3,
   EPI_COMPOSE_LDS = 4,
   EPI_SMOOTH_MAX = 5
 };
@@ -174,7 +174,11 @@ inline int64_t padded_voxels(int n0, int n1, int n2) {
 // Whether the corner-quad copy of a padded volume stays below 4 GiB (its
 // gathers use 32-bit byte offsets).
 inline bool quad_supported(int n0, int n1, int n2) {
-  return (uint64_t)padded_voxels(n0, n1, n2) * 16u < ((uint64_t)1 << 32);
+  // 32-bit byte offsets; padded plane size and padded indices below 2^24
+  // (the gathers multiply them in 24 bits)
+  const uint64_t p0 = (uint64_t)n0 + 2 * kPad, p1 = (uint64_t)n1 + 2 * kPad, p2 = (uint64_t)n2 + 2 * kPad;
+  return (uint64_t)padded_voxels(n0, n1, n2) * 16u < ((uint64_t)1 << 32) && p1 * p2 < ((uint64_t)1 << 24) &&
+         p0 < ((uint64_t)1 << 24);
 }
 // Gaussian radii: the streaming and brick kernels take 0..kMaxRadius as a
 // template parameter; launch_gauss runs radii up to kMaxWideRadius through

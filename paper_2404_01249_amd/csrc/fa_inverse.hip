@@ -464,6 +464,10 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
+  g1.partials = H->partials;     // record the cost, advance t
+  g1.n_partials = 2 * inv_blocks(L.n);
+  g1.loss_hist = H->loss_hist;
+  g1.loss_cap = H->loss_cap;
   FA_HIP(fa::launch_gauss(g1, H->rg, fa::EPI_SMOOTH_MAX, L.tsg, H->stream));
 
   fa::GaussArgs g2 = gs;   // e' = u + e(x + u), u = -eta s / (2M), in place over s
@@ -476,7 +480,7 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g2.tiles_x = L.tsc.tiles_x;
   FA_HIP(fa::launch_gauss(g2, 0, H->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE, L.tsc, H->stream));
 
-  fa::GaussArgs g3 = gs;   // e = G * e'; record the cost, advance t
+  fa::GaussArgs g3 = gs;   // e = G * e'
   g3.in = H->tmp;
   g3.out = H->e;
   g3.wts = H->wts + H->off_w;
@@ -484,11 +488,7 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;
-  g3.partials = H->partials;
-  g3.n_partials = 2 * inv_blocks(L.n);
-  g3.loss_hist = H->loss_hist;
-  g3.loss_cap = H->loss_cap;
-  FA_HIP(fa::launch_gauss(g3, H->rw, fa::EPI_STORE_FINAL, L.tsw, H->stream));
+  FA_HIP(fa::launch_gauss(g3, H->rw, fa::EPI_STORE, L.tsw, H->stream));
   return FA_OK;
 }
 
@@ -547,7 +547,7 @@ fa_status fa_inverse_set_schedule(fa_inverse H, int n_levels, const float* scale
     lv[i].tsg = fa::choose_tiling(lv[i].shape, fa::KIND_SMOOTH_MAX, fa::Tuning(),
                                   fa::gauss_cube_supported(H->rg, fa::EPI_SMOOTH_MAX));
     lv[i].tsw = fa::choose_tiling(lv[i].shape, fa::KIND_WARP_SMOOTH, fa::Tuning(),
-                                  fa::gauss_cube_supported(H->rw, fa::EPI_STORE_FINAL));
+                                  fa::gauss_cube_supported(H->rw, fa::EPI_STORE));
     lv[i].tsc = fa::choose_tiling(lv[i].shape, fa::KIND_COMPOSE, fa::Tuning(),
                                   H->p.eta <= 2.0f && fa::gauss_cube_supported(0, fa::EPI_COMPOSE_LDS));
     total += iters[i];

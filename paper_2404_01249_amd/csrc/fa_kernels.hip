@@ -6,11 +6,11 @@
 //            Gateaux gradient g = dL/dJ * grad_p I_m (Jacobian-free Eulerian
 //            descent, Section 4.4.2) and the Adam update (Section 4.4) ->
 //            m, v, direction a; per-workgroup loss partials.
-//   gauss  : s = G_sigma_grad * a stored, M = max |s|     (EPI_SMOOTH_MAX)
+//   gauss  : s = G_sigma_grad * a stored, M = max |s|; one workgroup records
+//            the loss and advances the Adam step count      (EPI_SMOOTH_MAX)
 //   gauss  : single tap: u = -eta s / (2M) (Appendix E), d' = u + d(x + u)
 //            (the retraction phi o (id + u) of Algorithm 1)  (EPI_COMPOSE_LDS)
-//   gauss  : d = G_sigma_warp * d'; the last workgroup records the loss and
-//            advances the Adam step count                   (EPI_STORE_FINAL)
+//   gauss  : d = G_sigma_warp * d'                          (EPI_STORE)
 //
 // Every streaming kernel gives a workgroup an in-plane tile (TY x TX columns
 // along n1, n2) and marches it along n0 over a chunk of planes.  Window sums
@@ -365,11 +365,13 @@ __device__ __forceinline__ void gather_issue(const float* __restrict__ f, const 
 // two aligned 16-byte loads (planes z and z+1 of its cell) instead of eight
 // 4-byte ones, and the corners arrive in gather_issue's order, so the values
 // and every result are the same.  Byte offsets are 32-bit unsigned (the quad
-// array stays below 4 GiB; the runtime checks it).
-__device__ __forceinline__ void quad_axis(int x, float dd, int n, unsigned stride_bytes, unsigned& lo, float& t) {
+// array stays below 4 GiB), and the padded plane size and every padded index
+// stay below 2^24, so the index products are full-rate 24-bit multiplies (the
+// runtime checks both: quad_supported).
+__device__ __forceinline__ void quad_axis(int x, float dd, int n, unsigned stride_quads, unsigned& lo, float& t) {
   dd = clamp_med3(dd, (float)(-x - kPad), (float)(n - x));
   const float f = floorf(dd);
-  lo = (unsigned)(x + kPad + (int)f) * stride_bytes;   // padded index in [0, n + kPad]
+  lo = __umul24((unsigned)(x + kPad + (int)f), stride_quads);   // padded index in [0, n + kPad]
   t = dd - f;
 }
 
@@ -377,11 +379,11 @@ __device__ __forceinline__ void gather_issue_quad(const float* __restrict__ q, i
                                                   int y, int x, float d0, float d1, float d2, Gather& g) {
   const unsigned p2 = (unsigned)(n2 + 2 * kPad), p1 = (unsigned)(n1 + 2 * kPad);
   unsigned l0, l1, l2;
-  quad_axis(z, d0, n0, p1 * p2 * 16u, l0, g.t0);
-  quad_axis(y, d1, n1, p2 * 16u, l1, g.t1);
-  quad_axis(x, d2, n2, 16u, l2, g.t2);
+  quad_axis(z, d0, n0, p1 * p2, l0, g.t0);
+  quad_axis(y, d1, n1, p2, l1, g.t1);
+  quad_axis(x, d2, n2, 1u, l2, g.t2);
   const char* b = reinterpret_cast<const char*>(q);
-  const unsigned off = l0 + l1 + l2;
+  const unsigned off = (l0 + l1 + l2) * 16u;
   const float4 lo = *reinterpret_cast<const float4*>(b + (size_t)off);
   const float4 hi = *reinterpret_cast<const float4*>(b + (size_t)(off + p1 * p2 * 16u));
   g.c[0] = lo.x;
@@ -862,36 +864,54 @@ __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)
 // before the current plane's passes; the composition epilogue issues its
 // gathers of d in one plane step and consumes them in the next.
 // ---------------------------------------------------------------------------
-// End of an iteration, in the last launch: the last workgroup to finish
-// records the iteration's loss from the gradient kernel's partials and
-// advances the Adam step count.  Everything it reads was written by earlier
-// launches, and no workgroup of this launch reads what it writes, so the
-// completion count needs no memory fences: only the atomic itself, which
-// hands the epilogue to exactly one workgroup.
+// The iteration's loss record and Adam step count, run at its end by one
+// workgroup of the direction-smoothing launch (EPI_SMOOTH_MAX, with A.partials
+// set): the gradient kernel before it has written every loss partial, and no
+// launch of the iteration after it reads t or the bias corrections (the next
+// iteration's gradient kernel does).  No other workgroup waits for it, and
+// the workgroup fetched its thread's partial (`first`, partial number
+// threadIdx.x) before its own work.  The partials are summed as 64-element
+// chunks, each by one wave with the same shuffle tree, and the chunk sums in
+// order by one thread: the sum does not depend on the workgroup size.
 template <int NT>
-__device__ __forceinline__ void finish_iteration(const GaussArgs& A, double* red, int* is_last, int nblocks) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(&A.ctl->ticket, 1u);
-    *is_last = (prev == (unsigned)nblocks - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (*is_last) {
-    double s = 0.0;
-    for (int i = tid; i < A.n_partials; i += NT) s += A.partials[i];
-    s = block_sum<NT>(s, red);
-    if (tid == 0) {
-      const int t = A.ctl->t;
-      const int it = A.ctl->iter;
-      if (A.loss_hist && it >= 0 && it < A.loss_cap) A.loss_hist[it] = (float)(-s * (double)A.inv_n);
-      A.ctl->iter = it + 1;
-      A.ctl->t = t + 1;
-      A.ctl->bc1 = (float)(1.0 - pow((double)A.ctl->beta1, (double)(t + 1)));
-      A.ctl->bc2 = (float)(1.0 - pow((double)A.ctl->beta2, (double)(t + 1)));
-      A.ctl->ticket = 0u;
+__device__ __forceinline__ void record_iteration(const GaussArgs& A, double first) {
+  static_assert(NT % 64 == 0, "whole waves");
+  constexpr int NW = NT / 64;
+  __shared__ double csum[64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int n = A.n_partials, nch = (n + 63) / 64;
+  double s = 0.0;
+  for (int c0 = 0; c0 < nch; c0 += 64) {   // rounds of at most 64 chunks
+    const int cend = min(nch, c0 + 64);
+    for (int c = c0 + wid; c < cend; c += NW) {
+      const int i = c * 64 + lane;
+      double v = c < NW ? first : (i < n ? A.partials[i] : 0.0);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if (lane == 0) csum[c - c0] = v;
     }
+    __syncthreads();
+    if (tid == 0)
+      for (int c = c0; c < cend; ++c) s += csum[c - c0];
+    __syncthreads();
   }
+  if (tid == 0) {
+    Ctl* C = A.ctl;
+    const int it = C->iter;
+    if (A.loss_hist && it >= 0 && it < A.loss_cap) A.loss_hist[it] = (float)(-s * (double)A.inv_n);
+    C->iter = it + 1;
+    C->t = C->t + 1;
+    const double p1 = C->bp1 * (double)C->beta1, p2 = C->bp2 * (double)C->beta2;
+    C->bp1 = p1;
+    C->bp2 = p2;
+    C->bc1 = (float)(1.0 - p1);
+    C->bc2 = (float)(1.0 - p2);
+  }
+}
+
+// The partial a recording workgroup's thread fetches before its own work.
+__device__ __forceinline__ double record_prefetch(const GaussArgs& A, bool rec) {
+  return rec && (int)threadIdx.x < A.n_partials ? A.partials[threadIdx.x] : 0.0;
 }
 
 template <int R, int TY, int TX, int EPI>
@@ -916,7 +936,6 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   float* bufx = glds + 3 * E;  // [3][XS]
   float* dring = glds + 3 * E + 3 * XS;  // [3 planes][3][DEP] (EPI_COMPOSE_LDS)
   __shared__ double red[NT / 64];
-  __shared__ int is_last;
 
   const int tid = threadIdx.x;
   int b = tile;
@@ -932,6 +951,10 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   const int oy = tid / TX, ox = tid % TX;
   const int gy = y0 + oy, gx = x0 + ox;
   const bool out_col = gy < n1 && gx < n2;
+  // the last tile (a chunk of the last planes, the shortest when the chunk
+  // length does not divide n0) records the iteration
+  const bool rec = EPI == EPI_SMOOTH_MAX && A.partials && tile == nblocks - 1;
+  const double pfirst = record_prefetch(A, rec);
 
   // clamped in-plane offsets of this thread's halo-tile columns
   int coff[CPT];
@@ -1101,7 +1124,7 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
       }
       const int idx = vidx(zo, gy, gx, n1, n2);
       const unsigned off = (unsigned)idx * 4u;
-      if (EPI == EPI_STORE || EPI == EPI_STORE_FINAL) {
+      if (EPI == EPI_STORE) {
         store_at(A.out, off, v0);
         store_at(A.out + N, off, v1);
         store_at(A.out + 2 * N, off, v2);
@@ -1158,7 +1181,7 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
   }
-  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last, nblocks);
+  if (rec) record_iteration<NT>(A, pfirst);
 }
 
 // ---------------------------------------------------------------------------
@@ -1453,7 +1476,6 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   float* reg = lds;            // [3][NR], later [3][NY]
   float* xo = lds + 3 * NR;    // [3][NX]
   __shared__ double red[NT / 64];
-  __shared__ int is_last;
 
   const int tid = threadIdx.x;
   int b = tile;
@@ -1464,6 +1486,10 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
   const int N = n0 * n1 * n2;
   const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
+  // the last brick (cut short by the volume's far corner, if any) records
+  // the iteration
+  const bool rec = EPI == EPI_SMOOTH_MAX && A.partials && tile == nblocks - 1;
+  const double pfirst = record_prefetch(A, rec);
 
   float w[L];
 #pragma unroll
@@ -1548,8 +1574,8 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
+    if (rec) record_iteration<NT>(A, pfirst);
   }
-  if (EPI == EPI_STORE_FINAL) finish_iteration<NT>(A, red, &is_last, nblocks);
 }
 
 // d' = u + d(x + u), u = -eta s / (2M), |u| <= 1 voxel, on a brick: d is
@@ -1910,8 +1936,8 @@ __global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ 
 // zeros), and each staged input is read from LDS once per thread instead of
 // once per tap.  One component is staged at a time.  The last pass (axis 0)
 // also runs the smoothing's epilogue (EPI): the max norm M of the result
-// (EPI_SMOOTH_MAX) or the loss record and step count (EPI_STORE_FINAL), as
-// the streaming kernels do; E carries the control block and loss fields.
+// (EPI_SMOOTH_MAX, with the loss record and step count), as the streaming
+// kernels do; E carries the control block and loss fields.
 constexpr int kWideRun = 32;
 template <int AX, int EPI>
 __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
@@ -1919,7 +1945,6 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
                                                        const GaussArgs E) {
   extern __shared__ float wl[];   // [kWideRun + L8][64], one component at a time
   __shared__ double red[4];
-  __shared__ int is_last;
   const int L8 = (2 * R + 1 + 7) / 8 * 8;
   const int LS = kWideRun + L8;
   const int lane = threadIdx.x & 63, j0 = threadIdx.x >> 6;
@@ -1932,6 +1957,10 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   const int64_t base = AX == 0 ? (int64_t)other * n2 : (int64_t)other * n1 * n2;
   const bool xin = x < n2;
   const int bo = 8 * j0;          // this thread's outputs, relative to a0
+  // the last workgroup records the iteration
+  const bool rec = EPI == EPI_SMOOTH_MAX && E.partials && blockIdx.x == gridDim.x - 1 &&
+                   blockIdx.y == gridDim.y - 1 && blockIdx.z == gridDim.z - 1;
+  const double pfirst = record_prefetch(E, rec);
   float v[3][8];
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();   // the previous component's reads are done
@@ -1970,9 +1999,8 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
     if (threadIdx.x == 0) atomicMax(&E.ctl->mbits, __float_as_uint(bm));
+    if (rec) record_iteration<256>(E, pfirst);
   }
-  if (EPI == EPI_STORE_FINAL)
-    finish_iteration<256>(E, red, &is_last, (int)(gridDim.x * gridDim.y * gridDim.z));
 }
 
 __global__ void k_blur_axis(const float* __restrict__ in, float* __restrict__ out, int n0, int n1,
@@ -2131,10 +2159,11 @@ __global__ void k_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int i
     if (iter >= 0) ctl->iter = iter;
     ctl->beta1 = beta1;
     ctl->beta2 = beta2;
-    ctl->bc1 = (float)(1.0 - pow((double)beta1, (double)t));
-    ctl->bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    ctl->bp1 = pow((double)beta1, (double)t);
+    ctl->bp2 = pow((double)beta2, (double)t);
+    ctl->bc1 = (float)(1.0 - ctl->bp1);
+    ctl->bc2 = (float)(1.0 - ctl->bp2);
     ctl->mbits = 0u;
-    ctl->ticket = 0u;
   }
 }
 
@@ -2219,7 +2248,6 @@ hipError_t gauss_launch_r(const GaussArgs& a, int epi, const Tiling& t, hipStrea
     case EPI_STORE: k_gauss<R, TY, TX, EPI_STORE><<<g, blk, sh, s>>>(a); break;
     case EPI_MAXNORM: k_gauss<R, TY, TX, EPI_MAXNORM><<<g, blk, sh, s>>>(a); break;
     case EPI_COMPOSE: k_gauss<R, TY, TX, EPI_COMPOSE><<<g, blk, sh, s>>>(a); break;
-    case EPI_STORE_FINAL: k_gauss<R, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(a); break;
     case EPI_COMPOSE_LDS: k_gauss<R, TY, TX, EPI_COMPOSE_LDS><<<g, blk, sh, s>>>(a); break;
     case EPI_SMOOTH_MAX: k_gauss<R, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(a); break;
     default: return hipErrorInvalidValue;
@@ -2250,7 +2278,7 @@ hipError_t gauss_cube_r(const GaussArgs& a, int epi, const Tiling& t, hipStream_
   const dim3 g(t.blocks()), blk(TZ * TY * TX);
   switch (epi) {
     case EPI_SMOOTH_MAX: k_gauss_cube<R, TZ, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(a); break;
-    case EPI_STORE_FINAL: k_gauss_cube<R, TZ, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(a); break;
+    case EPI_STORE: k_gauss_cube<R, TZ, TY, TX, EPI_STORE><<<g, blk, sh, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2359,7 +2387,7 @@ hipError_t gauss_batch_r(const BatchEntry<GaussArgs>* E, const int* owner, int t
   const size_t sh = gauss_lds<R, TY, TX>(epi == EPI_COMPOSE_LDS);
   switch (epi) {
     case EPI_SMOOTH_MAX: k_gauss_batch<R, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(E, owner); break;
-    case EPI_STORE_FINAL: k_gauss_batch<R, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(E, owner); break;
+    case EPI_STORE: k_gauss_batch<R, TY, TX, EPI_STORE><<<g, blk, sh, s>>>(E, owner); break;
     case EPI_COMPOSE_LDS:
     case EPI_COMPOSE:
       // the composition runs with the single tap (radius 0) only
@@ -2399,7 +2427,7 @@ hipError_t gauss_cube_batch_r(const BatchEntry<GaussArgs>* E, const int* owner, 
   const dim3 g(total), blk(TZ * TY * TX);
   switch (epi) {
     case EPI_SMOOTH_MAX: k_gauss_cube_batch<R, TZ, TY, TX, EPI_SMOOTH_MAX><<<g, blk, sh, s>>>(E, owner); break;
-    case EPI_STORE_FINAL: k_gauss_cube_batch<R, TZ, TY, TX, EPI_STORE_FINAL><<<g, blk, sh, s>>>(E, owner); break;
+    case EPI_STORE: k_gauss_cube_batch<R, TZ, TY, TX, EPI_STORE><<<g, blk, sh, s>>>(E, owner); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2430,7 +2458,7 @@ bool grad_cube_supported(int window) { return window == 1 || window == 3 || wind
 
 bool gauss_cube_supported(int radius, int epilogue) {
   if (epilogue == EPI_COMPOSE_LDS) return radius == 0;
-  return (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE_FINAL) && radius >= 0 && radius <= 3;
+  return (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE) && radius >= 0 && radius <= 3;
 }
 
 bool gauss_tile_supported(int ty, int tx) {
@@ -2465,7 +2493,7 @@ bool grad_batch_supported(int window, const Tiling& t) {
 bool gauss_batch_supported(int radius, int epilogue, const Tiling& t) {
   if (t.cube) return gauss_cube_supported(radius, epilogue);
   if (!gauss_tile_supported(t.ty, t.tx) || radius < 0 || radius > kMaxRadius) return false;
-  if (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE_FINAL) return true;
+  if (epilogue == EPI_SMOOTH_MAX || epilogue == EPI_STORE) return true;
   return (epilogue == EPI_COMPOSE_LDS || epilogue == EPI_COMPOSE) && radius == 0;
 }
 
@@ -2505,7 +2533,7 @@ hipError_t launch_gauss_narrow(const GaussArgs& a, int radius, int epilogue, con
 
 // Radius above kMaxRadius (sigma_grad or sigma_warp or the inverse's widths
 // above 2 voxels): three separable passes, the last with the epilogue (max
-// norm, or loss record and step count):
+// norm with the loss record and step count, or a plain store):
 //   in -> out (n2), out -> wide_tmp (n1), wide_tmp -> out (n0).
 // Needs a.wide_tmp distinct from a.in and a.out, a.in != a.out, and a tap
 // table a.wts of 2R + 1 taps followed by zeros up to a multiple of 16 (the
@@ -2513,7 +2541,7 @@ hipError_t launch_gauss_narrow(const GaussArgs& a, int radius, int epilogue, con
 hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const Tiling& t, hipStream_t s) {
   (void)t;
   if (radius > kMaxWideRadius || !a.wide_tmp || a.wide_tmp == a.in || a.wide_tmp == a.out || a.in == a.out ||
-      (epilogue != EPI_SMOOTH_MAX && epilogue != EPI_STORE_FINAL && epilogue != EPI_STORE))
+      (epilogue != EPI_SMOOTH_MAX && epilogue != EPI_STORE))
     return hipErrorInvalidValue;
   const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
   if (n0 > 65535 || n1 > 65535) return hipErrorInvalidValue;
@@ -2528,9 +2556,6 @@ hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const
   switch (epilogue) {
     case EPI_SMOOTH_MAX:
       k_field_wide_yz<0, EPI_SMOOTH_MAX><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
-      break;
-    case EPI_STORE_FINAL:
-      k_field_wide_yz<0, EPI_STORE_FINAL><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
       break;
     default:
       k_field_wide_yz<0, EPI_STORE><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);

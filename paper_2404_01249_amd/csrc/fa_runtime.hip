@@ -258,7 +258,8 @@ fa_status drain_profile(fa_pair P) {
 
 // The launches of one iteration of Algorithm 1 at level L: the fused
 // gradient (+ Adam), s = G_sigma_grad * a with M = max |s|, the composition
-// d' = u + d(x + u), and d = G_sigma_warp * d' with the loss record.
+// d' = u + d(x + u), and d = G_sigma_warp * d'.  The smoothing launch also
+// records the loss from the gradient kernel's partials and advances t.
 struct IterPlan {
   fa::GradArgs ga;
   Tiling tg;
@@ -318,6 +319,10 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
+  g1.partials = P->partials;
+  g1.n_partials = L.tg.blocks();
+  g1.loss_hist = P->loss_hist;
+  g1.loss_cap = P->loss_cap;
   it.tgs[0] = L.tsg;
   it.radius[0] = P->rg;
   it.epi[0] = fa::EPI_SMOOTH_MAX;
@@ -339,7 +344,7 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   // is staged in LDS instead of gathered
   it.epi[1] = P->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE;
 
-  fa::GaussArgs& g3 = it.g[2];  // d = G * d'; record loss, advance t
+  fa::GaussArgs& g3 = it.g[2];  // d = G * d'
   g3 = gs;
   g3.in = P->tmp;
   g3.out = P->d;
@@ -348,13 +353,9 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;
-  g3.partials = P->partials;
-  g3.n_partials = L.tg.blocks();
-  g3.loss_hist = P->loss_hist;
-  g3.loss_cap = P->loss_cap;
   it.tgs[2] = L.tsw;
   it.radius[2] = P->rw;
-  it.epi[2] = fa::EPI_STORE_FINAL;
+  it.epi[2] = fa::EPI_STORE;
 }
 
 fa_status launch_eulerian(fa_pair P, const Level& L) {
@@ -532,7 +533,7 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
       // one loss partial per workgroup: stay within the pair's partials buffer
       if (its[j].tg.blocks() > live[j]->partials_cap) its[j].tg = orig[q];
       its[j].ga.zc = its[j].tg.zc;
-      its[j].g[2].n_partials = its[j].tg.blocks();   // the loss record sums every gradient workgroup
+      its[j].g[0].n_partials = its[j].tg.blocks();   // the loss record sums every gradient workgroup
       args.push_back(&its[j].ga);
       nb.push_back(its[j].tg.blocks());
     }
@@ -928,7 +929,7 @@ fa_status fa_pair_set_schedule(fa_pair P, int n_levels, const float* scales, con
     lv[i].tsg = choose_tiling(lv[i].shape, fa::KIND_SMOOTH_MAX, P->tune[1],
                               fa::gauss_cube_supported(P->rg, fa::EPI_SMOOTH_MAX));
     lv[i].tsw = choose_tiling(lv[i].shape, fa::KIND_WARP_SMOOTH, P->tune[2],
-                              fa::gauss_cube_supported(P->rw, fa::EPI_STORE_FINAL));
+                              fa::gauss_cube_supported(P->rw, fa::EPI_STORE));
     lv[i].tsc = choose_tiling(lv[i].shape, fa::KIND_COMPOSE, P->tune[3],
                               P->p.eta <= 2.0f && fa::gauss_cube_supported(0, fa::EPI_COMPOSE_LDS));
     {
@@ -1447,7 +1448,7 @@ fa_status fa_pair_autotune(fa_pair P, int trials) {
   if (!P->scheduled) return fail(FA_ESTATE, "fa_pair_set_schedule has not been called");
   if (trials < 1 || trials > 100) return fail(FA_EINVAL, "trials must be in [1, 100]");
   FA_HIP(hipStreamSynchronize(P->stream));
-  // scratch control block: the timing launches update M, the ticket and the step count there
+  // scratch control block: the timing launches update M and the step count there
   Ctl* sctl = nullptr;
   FA_TRY(dalloc(&sctl, 1, "scratch control block"));
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1521,20 +1522,20 @@ fa_status fa_pair_autotune(fa_pair P, int trials) {
     for (int k = 0; k < 3 && st == FA_OK; ++k) {
       const bool cube_ok = k == 0   ? fa::gauss_cube_supported(P->rg, fa::EPI_SMOOTH_MAX)
                            : k == 1 ? (P->p.eta <= 2.0f && fa::gauss_cube_supported(0, fa::EPI_COMPOSE_LDS))
-                                    : fa::gauss_cube_supported(P->rw, fa::EPI_STORE_FINAL);
+                                    : fa::gauss_cube_supported(P->rw, fa::EPI_STORE);
       std::vector<Tiling> cs = tiling_candidates(L.shape, kinds[k], *slots[k], cube_ok);
       fa::GaussArgs g = it.g[k];
       g.ctl = sctl;
       if (k == 0) {
         g.in = P->a;
         g.out = P->tmp;
+        g.loss_hist = nullptr;   // the record runs (on the scratch control block) but stores no loss
+        g.n_partials = std::min(L.tg.blocks(), P->partials_cap);
       } else if (k == 1) {
         g.in = g.out = P->tmp;
       } else {
         g.in = P->tmp;
         g.out = P->a;
-        g.loss_hist = nullptr;
-        g.n_partials = std::min(L.tg.blocks(), P->partials_cap);
       }
       double bestk = 1e30;
       Tiling btk = *slots[k];
