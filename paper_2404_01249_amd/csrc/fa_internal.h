@@ -18,11 +18,17 @@ __device__ __forceinline__ float clamp_med3(float v, float lo, float hi) {
 // Per-pair control block in device memory.  Kernels of one iteration read
 // and update it so that a whole iteration can be replayed (for example from a
 // captured graph) without host involvement.
+// M = max |s| lives in kMSlots slots kMStride words apart (one per XCD, each
+// in its own 128-byte line): a workgroup's atomicMax goes to the slot of its
+// XCD, and readers take the maximum of the slots.  One address for every
+// workgroup serialises the atomics (about 10 ns each on this GPU, 10 us for
+// a thousand workgroups).
+constexpr int kMSlots = 8, kMStride = 32;
+
 struct Ctl {
   int t;                 // Adam step count of the iteration in flight (1-based)
   int iter;              // schedule iterations completed (index of the next loss)
   float bc1, bc2;        // 1 - beta1^t, 1 - beta2^t (from bp1, bp2)
-  unsigned int mbits;    // bit pattern of M = max |s| (non-negative float)
   float beta1, beta2;    // copies of the Adam constants for the t update
   float shift_i, shift_j;  // mean intensities of the fixed and moving inputs; LNCC
                            // is invariant to a global intensity shift, and
@@ -30,6 +36,8 @@ struct Ctl {
                            // window variances
   double bp1, bp2;       // beta1^t, beta2^t in double: pow at a level's start,
                          // then one product per iteration
+  // bit patterns of M (non-negative floats, so unsigned order is float order)
+  alignas(128) unsigned int mslot[kMSlots * kMStride];
 };
 
 // Tile geometry of one streaming launch: in-plane tile (TY x TX) along

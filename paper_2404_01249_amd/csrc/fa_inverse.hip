@@ -284,7 +284,7 @@ k_inv_dir(const float* __restrict__ d, const float* __restrict__ e, unsigned lon
           float adam_eps, int grad_only) {
   __shared__ double red[kInvThreads / 64];
   const int N = n0 * n1 * n2;
-  if (!grad_only && blockIdx.x == 0 && threadIdx.x == 0) ctl->mbits = 0u;
+  if (!grad_only && blockIdx.x == 0 && threadIdx.x < fa::kMSlots) ctl->mslot[threadIdx.x * fa::kMStride] = 0u;
   const float ibc1 = grad_only ? 1.0f : 1.0f / ctl->bc1;
   const float ibc2 = grad_only ? 1.0f : 1.0f / ctl->bc2;
   double loss = 0.0;

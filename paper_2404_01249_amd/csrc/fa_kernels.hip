@@ -29,6 +29,23 @@ __device__ __forceinline__ int vidx(int z, int y, int x, int n1, int n2) {
   return (z * n1 + y) * n2 + x;
 }
 
+// M = max |s| over the slots of Ctl::mslot: cleared by threads 0..kMSlots-1
+// of one workgroup, raised with one atomicMax per workgroup on the slot of
+// its XCD (workgroups go to the XCDs round robin by linear index), read as
+// the largest slot.
+__device__ __forceinline__ void m_clear(Ctl* c, int tid) {
+  if (tid < kMSlots) c->mslot[tid * kMStride] = 0u;
+}
+__device__ __forceinline__ void m_raise(Ctl* c, float bm, unsigned linear_block) {
+  atomicMax(&c->mslot[(linear_block % kMSlots) * kMStride], __float_as_uint(bm));
+}
+__device__ __forceinline__ float m_value(const Ctl* c) {
+  unsigned m = c->mslot[0];
+#pragma unroll
+  for (int j = 1; j < kMSlots; ++j) m = max(m, c->mslot[j * kMStride]);
+  return __uint_as_float(m);
+}
+
 // Cell index and fraction of a sample coordinate, plus whether the lower and
 // upper corners lie on the grid.  Coordinates far outside are clamped first
 // (all corners are then off the grid anyway), which also keeps the integer
@@ -554,7 +571,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   }
 
   const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
-  if (A.mode == 0 && tile == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
+  if (A.mode == 0 && tile == 0) m_clear(A.ctl, tid);  // M of this iteration
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
   const float gsc = (A.mode == 1 && A.gscale) ? *A.gscale : 1.0f;
   float lacc = 0.0f;   // this thread's cc sum over at most 2 zc columns
@@ -977,7 +994,7 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
 
   float scale = 0.0f;
   if (EPI == EPI_COMPOSE || EPI == EPI_COMPOSE_LDS) {
-    const float M = __uint_as_float(A.ctl->mbits);
+    const float M = m_value(A.ctl);
     scale = M > 0.0f ? -A.eta / (2.0f * M) : 0.0f;
   }
   float mx = 0.0f;
@@ -1179,7 +1196,7 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
 
   if (EPI == EPI_MAXNORM || EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
-    if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
+    if (tid == 0) m_raise(A.ctl, bm, blockIdx.x);
   }
   if (rec) record_iteration<NT>(A, pfirst);
 }
@@ -1233,7 +1250,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
   const int N = n0 * n1 * n2;
   const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
-  if (A.mode == 0 && tile == 0 && tid == 0) A.ctl->mbits = 0u;  // M of this iteration
+  if (A.mode == 0 && tile == 0) m_clear(A.ctl, tid);  // M of this iteration
 
   // the thread's own output voxel: I, J and grad_p I_m, Adam moments
   const int tz = tid / (TY * TX), tr = tid - tz * (TY * TX);
@@ -1573,7 +1590,7 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   }
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
-    if (tid == 0) atomicMax(&A.ctl->mbits, __float_as_uint(bm));
+    if (tid == 0) m_raise(A.ctl, bm, blockIdx.x);
     if (rec) record_iteration<NT>(A, pfirst);
   }
 }
@@ -1618,7 +1635,7 @@ __device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int 
       lds[2 * DE + c] = dv[k][2];
     }
   }
-  const float M = __uint_as_float(A.ctl->mbits);
+  const float M = m_value(A.ctl);
   const float scale = M > 0.0f ? -A.eta / (2.0f * M) : 0.0f;
   const int tz = tid / (TY * TX), r = tid - tz * (TY * TX);
   const int ty = r / TX, tx = r - ty * TX;
@@ -1825,7 +1842,7 @@ k_eulerian_adam(float* __restrict__ ga, const float* __restrict__ d, float* __re
                 float* __restrict__ v, Ctl* ctl, int n0, int n1, int n2, float beta1, float beta2,
                 float adam_eps) {
   const int N = n0 * n1 * n2;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mbits = 0u;   // M of this iteration
+  if (blockIdx.x == 0) m_clear(ctl, threadIdx.x);   // M of this iteration
   const float ibc1 = 1.0f / ctl->bc1, ibc2 = 1.0f / ctl->bc2;
   const int plane = n1 * n2;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
@@ -1998,7 +2015,7 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   }
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
-    if (threadIdx.x == 0) atomicMax(&E.ctl->mbits, __float_as_uint(bm));
+    if (threadIdx.x == 0) m_raise(E.ctl, bm, blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
     if (rec) record_iteration<256>(E, pfirst);
   }
 }
@@ -2163,7 +2180,7 @@ __global__ void k_ctl_init(Ctl* ctl, float beta1, float beta2, int t_done, int i
     ctl->bp2 = pow((double)beta2, (double)t);
     ctl->bc1 = (float)(1.0 - ctl->bp1);
     ctl->bc2 = (float)(1.0 - ctl->bp2);
-    ctl->mbits = 0u;
+    for (int j = 0; j < kMSlots; ++j) ctl->mslot[j * kMStride] = 0u;
   }
 }
 

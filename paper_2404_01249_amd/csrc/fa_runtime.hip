@@ -1319,7 +1319,9 @@ fa_status fa_pair_get_step_norm(fa_pair P, float* m_host) {
   Ctl c;
   FA_HIP(hipMemcpyAsync(&c, P->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
   FA_HIP(hipStreamSynchronize(P->stream));
-  std::memcpy(m_host, &c.mbits, sizeof(float));
+  unsigned m = 0u;   // M is the largest slot (fa_internal.h)
+  for (int j = 0; j < fa::kMSlots; ++j) m = std::max(m, c.mslot[j * fa::kMStride]);
+  std::memcpy(m_host, &m, sizeof(float));
   return FA_OK;
 }
 
