@@ -54,6 +54,11 @@ struct Tiling {
 };
 constexpr int kCubeZ = 4, kCubeY = 8, kCubeX = 16;   // brick of a cube launch
 
+// Which launch after the gradient kernel records an iteration's loss and
+// advances its step count (its GaussArgs carry the loss partials): the warp
+// smoothing (2) when it is a brick launch, else the composition (1).
+inline int record_launch(const Tiling& warp_smoothing) { return warp_smoothing.cube ? 2 : 1; }
+
 // ---- fused gradient (+ Adam) kernel -------------------------------------
 struct GradArgs {
   const float* fixed;

@@ -464,10 +464,6 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
-  g1.partials = H->partials;     // record the cost, advance t
-  g1.n_partials = 2 * inv_blocks(L.n);
-  g1.loss_hist = H->loss_hist;
-  g1.loss_cap = H->loss_cap;
   FA_HIP(fa::launch_gauss(g1, H->rg, fa::EPI_SMOOTH_MAX, L.tsg, H->stream));
 
   fa::GaussArgs g2 = gs;   // e' = u + e(x + u), u = -eta s / (2M), in place over s
@@ -478,7 +474,6 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g2.zc = L.tsc.zc;
   g2.tiles_y = L.tsc.tiles_y;
   g2.tiles_x = L.tsc.tiles_x;
-  FA_HIP(fa::launch_gauss(g2, 0, H->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE, L.tsc, H->stream));
 
   fa::GaussArgs g3 = gs;   // e = G * e'
   g3.in = H->tmp;
@@ -488,6 +483,16 @@ fa_status launch_iteration(fa_inverse H, const ILevel& L) {
   g3.zc = L.tsw.zc;
   g3.tiles_y = L.tsw.tiles_y;
   g3.tiles_x = L.tsw.tiles_x;
+
+  // the cost record and step count, in the launch the registration uses
+  fa::GaussArgs& gr = fa::record_launch(L.tsw) == 2 ? g3 : g2;
+  gr.partials = H->partials;
+  gr.n_partials = 2 * inv_blocks(L.n);
+  gr.loss_hist = H->loss_hist;
+  gr.loss_cap = H->loss_cap;
+
+  FA_HIP(fa::launch_gauss(g2, 0, H->p.eta <= 2.0f ? fa::EPI_COMPOSE_LDS : fa::EPI_COMPOSE, L.tsc, H->stream));
+
   FA_HIP(fa::launch_gauss(g3, H->rw, fa::EPI_STORE, L.tsw, H->stream));
   return FA_OK;
 }

@@ -6,11 +6,12 @@
 //            Gateaux gradient g = dL/dJ * grad_p I_m (Jacobian-free Eulerian
 //            descent, Section 4.4.2) and the Adam update (Section 4.4) ->
 //            m, v, direction a; per-workgroup loss partials.
-//   gauss  : s = G_sigma_grad * a stored, M = max |s|; one workgroup records
-//            the loss and advances the Adam step count      (EPI_SMOOTH_MAX)
+//   gauss  : s = G_sigma_grad * a stored, M = max |s|     (EPI_SMOOTH_MAX)
 //   gauss  : single tap: u = -eta s / (2M) (Appendix E), d' = u + d(x + u)
 //            (the retraction phi o (id + u) of Algorithm 1)  (EPI_COMPOSE_LDS)
 //   gauss  : d = G_sigma_warp * d'                          (EPI_STORE)
+// The first workgroup of the composition, or of the warp smoothing where that
+// is a brick launch, also records the loss and advances the Adam step count.
 //
 // Every streaming kernel gives a workgroup an in-plane tile (TY x TX columns
 // along n1, n2) and marches it along n0 over a chunk of planes.  Window sums
@@ -881,28 +882,36 @@ __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)
 // before the current plane's passes; the composition epilogue issues its
 // gathers of d in one plane step and consumes them in the next.
 // ---------------------------------------------------------------------------
-// The iteration's loss record and Adam step count, run at its end by one
-// workgroup of the direction-smoothing launch (EPI_SMOOTH_MAX, with A.partials
-// set): the gradient kernel before it has written every loss partial, and no
-// launch of the iteration after it reads t or the bias corrections (the next
-// iteration's gradient kernel does).  No other workgroup waits for it, and
-// the workgroup fetched its thread's partial (`first`, partial number
-// threadIdx.x) before its own work.  The partials are summed as 64-element
+// The iteration's loss record and Adam step count, run before its own work by
+// the first workgroup of one launch after the gradient kernel (the launch
+// whose GaussArgs carry the partials): the composition, or the warp smoothing
+// where that is a brick launch (it costs the brick composition 0.6 us and the
+// brick smoothing 0.1 us).  The gradient kernel of the iteration has written
+// every loss partial, and no launch reads t or the bias corrections before
+// the next iteration's gradient kernel.  No other workgroup waits for it, and
+// the first workgroup is dispatched first.  The streaming smoothing launches
+// never take it: inlined there, its registers cost occupancy or load
+// pipelining at some radii.  The composition has registers to spare.  The partials are summed as 64-element
 // chunks, each by one wave with the same shuffle tree, and the chunk sums in
 // order by one thread: the sum does not depend on the workgroup size.
 template <int NT>
-__device__ __forceinline__ void record_iteration(const GaussArgs& A, double first) {
+__device__ __forceinline__ void record_iteration(const GaussArgs& A) {
   static_assert(NT % 64 == 0, "whole waves");
   constexpr int NW = NT / 64;
   __shared__ double csum[64];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int n = A.n_partials, nch = (n + 63) / 64;
+  // the counters are fetched with the partials: one memory round trip
+  Ctl* C = A.ctl;
+  const int it = C->iter, t = C->t;
+  const double bp1 = C->bp1, bp2 = C->bp2;
+  const float b1 = C->beta1, b2 = C->beta2;
   double s = 0.0;
   for (int c0 = 0; c0 < nch; c0 += 64) {   // rounds of at most 64 chunks
     const int cend = min(nch, c0 + 64);
     for (int c = c0 + wid; c < cend; c += NW) {
       const int i = c * 64 + lane;
-      double v = c < NW ? first : (i < n ? A.partials[i] : 0.0);
+      double v = i < n ? A.partials[i] : 0.0;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
       if (lane == 0) csum[c - c0] = v;
@@ -913,22 +922,15 @@ __device__ __forceinline__ void record_iteration(const GaussArgs& A, double firs
     __syncthreads();
   }
   if (tid == 0) {
-    Ctl* C = A.ctl;
-    const int it = C->iter;
     if (A.loss_hist && it >= 0 && it < A.loss_cap) A.loss_hist[it] = (float)(-s * (double)A.inv_n);
     C->iter = it + 1;
-    C->t = C->t + 1;
-    const double p1 = C->bp1 * (double)C->beta1, p2 = C->bp2 * (double)C->beta2;
+    C->t = t + 1;
+    const double p1 = bp1 * (double)b1, p2 = bp2 * (double)b2;
     C->bp1 = p1;
     C->bp2 = p2;
     C->bc1 = (float)(1.0 - p1);
     C->bc2 = (float)(1.0 - p2);
   }
-}
-
-// The partial a recording workgroup's thread fetches before its own work.
-__device__ __forceinline__ double record_prefetch(const GaussArgs& A, bool rec) {
-  return rec && (int)threadIdx.x < A.n_partials ? A.partials[threadIdx.x] : 0.0;
 }
 
 template <int R, int TY, int TX, int EPI>
@@ -955,6 +957,8 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
+  // the first tile of the composition records the iteration before its own work
+  if ((EPI == EPI_COMPOSE_LDS || EPI == EPI_COMPOSE) && A.partials && tile == 0) record_iteration<NT>(A);
   int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
@@ -968,10 +972,6 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
   const int oy = tid / TX, ox = tid % TX;
   const int gy = y0 + oy, gx = x0 + ox;
   const bool out_col = gy < n1 && gx < n2;
-  // the last tile (a chunk of the last planes, the shortest when the chunk
-  // length does not divide n0) records the iteration
-  const bool rec = EPI == EPI_SMOOTH_MAX && A.partials && tile == nblocks - 1;
-  const double pfirst = record_prefetch(A, rec);
 
   // clamped in-plane offsets of this thread's halo-tile columns
   int coff[CPT];
@@ -1198,7 +1198,6 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) m_raise(A.ctl, bm, blockIdx.x);
   }
-  if (rec) record_iteration<NT>(A, pfirst);
 }
 
 // ---------------------------------------------------------------------------
@@ -1495,6 +1494,8 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
+  // the first brick of a warp smoothing that records the iteration does so first
+  if (EPI == EPI_STORE && A.partials && tile == 0) record_iteration<NT>(A);
   int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
@@ -1503,10 +1504,6 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
   const int N = n0 * n1 * n2;
   const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
-  // the last brick (cut short by the volume's far corner, if any) records
-  // the iteration
-  const bool rec = EPI == EPI_SMOOTH_MAX && A.partials && tile == nblocks - 1;
-  const double pfirst = record_prefetch(A, rec);
 
   float w[L];
 #pragma unroll
@@ -1591,7 +1588,6 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
     if (tid == 0) m_raise(A.ctl, bm, blockIdx.x);
-    if (rec) record_iteration<NT>(A, pfirst);
   }
 }
 
@@ -1604,6 +1600,8 @@ __device__ __forceinline__ void compose_cube_body(const GaussArgs& A, const int 
   constexpr int DZ = TZ + 2, DY = TY + 2, DX = TX + 2, DE = DZ * DY * DX;
   extern __shared__ float lds[];   // [3][DE]
   const int tid = threadIdx.x;
+  // the first brick records the iteration before its own work
+  if (A.partials && tile == 0) record_iteration<NT>(A);
   int b = tile;
   const int bx = b % A.tiles_x;
   b /= A.tiles_x;
@@ -1953,8 +1951,7 @@ __global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ 
 // zeros), and each staged input is read from LDS once per thread instead of
 // once per tap.  One component is staged at a time.  The last pass (axis 0)
 // also runs the smoothing's epilogue (EPI): the max norm M of the result
-// (EPI_SMOOTH_MAX, with the loss record and step count), as the streaming
-// kernels do; E carries the control block and loss fields.
+// (EPI_SMOOTH_MAX), as the streaming kernels do; E carries the control block.
 constexpr int kWideRun = 32;
 template <int AX, int EPI>
 __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
@@ -1974,10 +1971,6 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   const int64_t base = AX == 0 ? (int64_t)other * n2 : (int64_t)other * n1 * n2;
   const bool xin = x < n2;
   const int bo = 8 * j0;          // this thread's outputs, relative to a0
-  // the last workgroup records the iteration
-  const bool rec = EPI == EPI_SMOOTH_MAX && E.partials && blockIdx.x == gridDim.x - 1 &&
-                   blockIdx.y == gridDim.y - 1 && blockIdx.z == gridDim.z - 1;
-  const double pfirst = record_prefetch(E, rec);
   float v[3][8];
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();   // the previous component's reads are done
@@ -2016,7 +2009,6 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
     if (threadIdx.x == 0) m_raise(E.ctl, bm, blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
-    if (rec) record_iteration<256>(E, pfirst);
   }
 }
 
@@ -2550,7 +2542,7 @@ hipError_t launch_gauss_narrow(const GaussArgs& a, int radius, int epilogue, con
 
 // Radius above kMaxRadius (sigma_grad or sigma_warp or the inverse's widths
 // above 2 voxels): three separable passes, the last with the epilogue (max
-// norm with the loss record and step count, or a plain store):
+// norm, or a plain store):
 //   in -> out (n2), out -> wide_tmp (n1), wide_tmp -> out (n0).
 // Needs a.wide_tmp distinct from a.in and a.out, a.in != a.out, and a tap
 // table a.wts of 2R + 1 taps followed by zeros up to a multiple of 16 (the

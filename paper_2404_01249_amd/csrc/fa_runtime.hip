@@ -258,8 +258,9 @@ fa_status drain_profile(fa_pair P) {
 
 // The launches of one iteration of Algorithm 1 at level L: the fused
 // gradient (+ Adam), s = G_sigma_grad * a with M = max |s|, the composition
-// d' = u + d(x + u), and d = G_sigma_warp * d'.  The smoothing launch also
-// records the loss from the gradient kernel's partials and advances t.
+// d' = u + d(x + u), and d = G_sigma_warp * d'.  One launch also records the
+// loss from the gradient kernel's partials and advances t: the warp smoothing
+// when it is a brick launch, else the composition.
 struct IterPlan {
   fa::GradArgs ga;
   Tiling tg;
@@ -319,10 +320,6 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   g1.zc = L.tsg.zc;
   g1.tiles_y = L.tsg.tiles_y;
   g1.tiles_x = L.tsg.tiles_x;
-  g1.partials = P->partials;
-  g1.n_partials = L.tg.blocks();
-  g1.loss_hist = P->loss_hist;
-  g1.loss_cap = P->loss_cap;
   it.tgs[0] = L.tsg;
   it.radius[0] = P->rg;
   it.epi[0] = fa::EPI_SMOOTH_MAX;
@@ -356,6 +353,13 @@ void plan_iteration(fa_pair P, const Level& L, IterPlan& it, const float* fixed 
   it.tgs[2] = L.tsw;
   it.radius[2] = P->rw;
   it.epi[2] = fa::EPI_STORE;
+
+  // the loss record and step count
+  fa::GaussArgs& gr = it.g[record_launch(L.tsw)];
+  gr.partials = P->partials;
+  gr.n_partials = L.tg.blocks();
+  gr.loss_hist = P->loss_hist;
+  gr.loss_cap = P->loss_cap;
 }
 
 fa_status launch_eulerian(fa_pair P, const Level& L) {
@@ -533,7 +537,8 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
       // one loss partial per workgroup: stay within the pair's partials buffer
       if (its[j].tg.blocks() > live[j]->partials_cap) its[j].tg = orig[q];
       its[j].ga.zc = its[j].tg.zc;
-      its[j].g[0].n_partials = its[j].tg.blocks();   // the loss record sums every gradient workgroup
+      // the loss record sums every gradient workgroup
+      its[j].g[record_launch(its[j].tgs[2])].n_partials = its[j].tg.blocks();
       args.push_back(&its[j].ga);
       nb.push_back(its[j].tg.blocks());
     }
@@ -1531,13 +1536,15 @@ fa_status fa_pair_autotune(fa_pair P, int trials) {
       if (k == 0) {
         g.in = P->a;
         g.out = P->tmp;
-        g.loss_hist = nullptr;   // the record runs (on the scratch control block) but stores no loss
-        g.n_partials = std::min(L.tg.blocks(), P->partials_cap);
       } else if (k == 1) {
         g.in = g.out = P->tmp;
       } else {
         g.in = P->tmp;
         g.out = P->a;
+      }
+      if (g.partials) {   // the record runs (on the scratch control block) but stores no loss
+        g.loss_hist = nullptr;
+        g.n_partials = std::min(L.tg.blocks(), P->partials_cap);
       }
       double bestk = 1e30;
       Tiling btk = *slots[k];
