@@ -130,9 +130,10 @@ hipError_t launch_gauss(const GaussArgs& a, int radius, int epilogue, const Tili
 // Batched forms: `total` workgroups over the entries E (device memory) with
 // owner (device memory, `total` ints); t gives the template parameters only
 // (tile shape, brick or march) and must be the tiling of every entry.
-// quad: every entry's moving_quad is set (the corner-quad gathers).
+// quad: every entry's moving_quad is set (the corner-quad gathers).  adam:
+// every entry's mode is 0 (gradient and Adam; a kernel specialised for it).
 hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
-                             const Tiling& t, bool quad, hipStream_t s);
+                             const Tiling& t, bool quad, bool adam, hipStream_t s);
 hipError_t launch_gauss_batch(const BatchEntry<GaussArgs>* E, const int* owner, int total, int radius,
                               int epilogue, const Tiling& t, hipStream_t s);
 // Whether a batched form exists for these parameters.

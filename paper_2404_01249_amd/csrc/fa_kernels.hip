@@ -487,8 +487,10 @@ __device__ __forceinline__ bool slot_coords(int tid, int slot, int& ey, int& ex)
   }
 }
 
-template <int W, int TY, int TX, bool PIPE, bool QUAD = false>
+// MODE: A.mode fixed at compile time (0, 1 or 2), or -1 to read it at run time.
+template <int W, int TY, int TX, bool PIPE, bool QUAD = false, int MODE = -1>
 __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
+  const int mode = MODE >= 0 ? MODE : A.mode;
   constexpr int R = W / 2;
   constexpr int NT = TY * TX;
   constexpr int E1Y = TY + 4 * R, E1X = TX + 4 * R, E1 = E1Y * E1X;
@@ -572,9 +574,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   }
 
   const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
-  if (A.mode == 0 && tile == 0) m_clear(A.ctl, tid);  // M of this iteration
+  if (mode == 0 && tile == 0) m_clear(A.ctl, tid);  // M of this iteration
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
-  const float gsc = (A.mode == 1 && A.gscale) ? *A.gscale : 1.0f;
+  const float gsc = (mode == 1 && A.gscale) ? *A.gscale : 1.0f;
   float lacc = 0.0f;   // this thread's cc sum over at most 2 zc columns
 
   const int zs = z0 - 2 * R, ze = z1 + 2 * R;
@@ -795,7 +797,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
       const int zc2 = zc1 - R;
       if (zc2 >= z0 && out_col) {
         const unsigned off = (unsigned)vidx(zc2, gy, gx, n1, n2) * 4u;
-        if (A.mode == 0 && !mv_ready) {
+        if (mode == 0 && !mv_ready) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
             pm[q] = load_at(A.m + q * N, off);
@@ -822,7 +824,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
           g[1] = dl * greg[1][0];
           g[2] = dl * greg[2][0];
         }
-        if (A.mode == 0) {
+        if (mode == 0) {
           const float b1 = A.beta1, b2 = A.beta2;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
@@ -842,7 +844,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
               pv[q] = load_at(A.v + q * N, noff);
             }
           }
-        } else if (A.mode == 1) {
+        } else if (mode == 1) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) store_at(A.out + q * N, off, g[q] * gsc);
         }
@@ -870,9 +872,9 @@ __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
 
 // The same kernel compiled for two workgroups per CU (at most 128 VGPRs);
 // used where that fits without spilling.
-template <int W, int TY, int TX, bool PIPE, bool QUAD = false>
+template <int W, int TY, int TX, bool PIPE, bool QUAD = false, int MODE = -1>
 __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4))) k_grad_o4(const GradArgs A) {
-  grad_body<W, TY, TX, PIPE, QUAD>(A, xcd_tile(blockIdx.x, gridDim.x));
+  grad_body<W, TY, TX, PIPE, QUAD, MODE>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1761,13 +1763,13 @@ __global__ void __launch_bounds__(TY * TX) k_grad_batch(const BatchEntry<GradArg
   grad_body<W, TY, TX, true>(A, tile);
 }
 
-template <int W, int TY, int TX, bool QUAD = false>
+template <int W, int TY, int TX, bool QUAD = false, int MODE = -1>
 __global__ void __launch_bounds__(TY * TX) __attribute__((amdgpu_waves_per_eu(4)))
 k_grad_o4_batch(const BatchEntry<GradArgs>* __restrict__ E, const int* __restrict__ owner) {
   GradArgs A;
   int nb;
   const int tile = batch_entry(E, owner, A, nb);
-  grad_body<W, TY, TX, true, QUAD>(A, tile);
+  grad_body<W, TY, TX, true, QUAD, MODE>(A, tile);
 }
 
 template <int R, int TY, int TX, int EPI>
@@ -2228,6 +2230,7 @@ hipError_t grad_launch_t(const GradArgs& a, const Tiling& t, hipStream_t s) {
   const dim3 g(t.blocks()), blk(TY * TX);
   if constexpr (occ2) {
     if (t.variant == 2) k_grad_o4<W, TY, TX, false><<<g, blk, sh, s>>>(a);
+    else if (a.moving_quad && a.mode == 0) k_grad_o4<W, TY, TX, true, true, 0><<<g, blk, sh, s>>>(a);
     else if (a.moving_quad) k_grad_o4<W, TY, TX, true, true><<<g, blk, sh, s>>>(a);
     else k_grad_o4<W, TY, TX, true><<<g, blk, sh, s>>>(a);
   } else {
@@ -2342,12 +2345,14 @@ hipError_t grad_launch_cube(const GradArgs& a, int window, const Tiling& t, hipS
 
 // ---- batched launches ------------------------------------------------------
 template <int W, int TY, int TX>
-hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int total, bool quad, hipStream_t s) {
+hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int total, bool quad, bool adam,
+                        hipStream_t s) {
   constexpr size_t sh = grad_lds<W, TY, TX>();
   constexpr bool occ2 = (W <= 5) && TY == 16 && TX == 32;
   const dim3 g(total), blk(TY * TX);
   if constexpr (occ2) {
-    if (quad) k_grad_o4_batch<W, TY, TX, true><<<g, blk, sh, s>>>(E, owner);
+    if (quad && adam) k_grad_o4_batch<W, TY, TX, true, 0><<<g, blk, sh, s>>>(E, owner);
+    else if (quad) k_grad_o4_batch<W, TY, TX, true><<<g, blk, sh, s>>>(E, owner);
     else k_grad_o4_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
   } else {
     k_grad_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
@@ -2357,13 +2362,13 @@ hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int tot
 
 template <int TY, int TX>
 hipError_t grad_batch_tile(const BatchEntry<GradArgs>* E, const int* owner, int total, int window, bool quad,
-                           hipStream_t s) {
+                           bool adam, hipStream_t s) {
   switch (window) {
-    case 1: return grad_batch_t<1, TY, TX>(E, owner, total, quad, s);
-    case 3: return grad_batch_t<3, TY, TX>(E, owner, total, quad, s);
-    case 5: return grad_batch_t<5, TY, TX>(E, owner, total, quad, s);
-    case 7: return grad_batch_t<7, TY, TX>(E, owner, total, quad, s);
-    case 9: return grad_batch_t<9, TY, TX>(E, owner, total, quad, s);
+    case 1: return grad_batch_t<1, TY, TX>(E, owner, total, quad, adam, s);
+    case 3: return grad_batch_t<3, TY, TX>(E, owner, total, quad, adam, s);
+    case 5: return grad_batch_t<5, TY, TX>(E, owner, total, quad, adam, s);
+    case 7: return grad_batch_t<7, TY, TX>(E, owner, total, quad, adam, s);
+    case 9: return grad_batch_t<9, TY, TX>(E, owner, total, quad, adam, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2507,7 +2512,7 @@ bool gauss_batch_supported(int radius, int epilogue, const Tiling& t) {
 }
 
 hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, int total, int window,
-                             const Tiling& t, bool quad, hipStream_t s) {
+                             const Tiling& t, bool quad, bool adam, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   if (t.cube) {
     switch (window) {
@@ -2517,8 +2522,8 @@ hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, in
       default: return hipErrorInvalidValue;
     }
   }
-  if (t.ty == 16 && t.tx == 32) return grad_batch_tile<16, 32>(E, owner, total, window, quad, s);
-  if (t.ty == 8 && t.tx == 32) return grad_batch_tile<8, 32>(E, owner, total, window, quad, s);
+  if (t.ty == 16 && t.tx == 32) return grad_batch_tile<16, 32>(E, owner, total, window, quad, adam, s);
+  if (t.ty == 8 && t.tx == 32) return grad_batch_tile<8, 32>(E, owner, total, window, quad, adam, s);
   return hipErrorInvalidValue;
 }
 

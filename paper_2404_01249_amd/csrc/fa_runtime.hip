@@ -448,6 +448,7 @@ struct BatchLaunch {
   size_t own_off;
   int total;       // workgroups of the launch
   bool quad = false;   // gradient: the entries gather from corner quads
+  bool adam = false;   // gradient: every entry runs mode 0 (gradient and Adam)
   // radius above 6: no batched form; each entry's launches run one after
   // another from these host-side arguments instead
   std::vector<fa::GaussArgs> singles;
@@ -509,7 +510,8 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
     std::vector<size_t> mem;
     for (size_t j = i; j < n; ++j) {
       if (taken[j] || its[j].window != its[i].window || !same_form(its[j].tg, its[i].tg) ||
-          (its[j].ga.moving_quad != nullptr) != (its[i].ga.moving_quad != nullptr))
+          (its[j].ga.moving_quad != nullptr) != (its[i].ga.moving_quad != nullptr) ||
+          (its[j].ga.mode == 0) != (its[i].ga.mode == 0))
         continue;
       taken[j] = 1;
       mem.push_back(j);
@@ -544,6 +546,7 @@ fa_status build_batch_tables(const std::vector<fa_pair>& live, BatchTables& bt) 
     }
     append_launch(bt, 0, its[i].tg, its[i].window, 0, args, nb);
     bt.launches.back().quad = its[i].ga.moving_quad != nullptr;
+    bt.launches.back().adam = its[i].ga.mode == 0;
   }
   // stages 1 to 3, grouped by radius, epilogue and tiling form
   static const fa::KernelKind kinds[3] = {fa::KIND_SMOOTH_MAX, fa::KIND_COMPOSE, fa::KIND_WARP_SMOOTH};
@@ -627,7 +630,7 @@ fa_status launch_batch_iteration(const std::vector<fa_pair>& live, const BatchTa
     const int* own = reinterpret_cast<const int*>(base + bl.own_off);
     if (bl.stage == 0) {
       const auto* E = reinterpret_cast<const fa::BatchEntry<fa::GradArgs>*>(base + bl.ent_off);
-      FA_HIP(fa::launch_grad_batch(E, own, bl.total, bl.param, bl.t, bl.quad, s));
+      FA_HIP(fa::launch_grad_batch(E, own, bl.total, bl.param, bl.t, bl.quad, bl.adam, s));
     } else {
       const auto* E = reinterpret_cast<const fa::BatchEntry<fa::GaussArgs>*>(base + bl.ent_off);
       FA_HIP(fa::launch_gauss_batch(E, own, bl.total, bl.param, bl.epi, bl.t, s));
