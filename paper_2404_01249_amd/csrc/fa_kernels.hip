@@ -1228,8 +1228,10 @@ struct GradCubeShape {
   static constexpr size_t lds_bytes = sizeof(float) * (size_t)(SA + SB);
 };
 
-template <int W, int TZ, int TY, int TX, bool QUAD = false>
+// MODE as for grad_body: A.mode fixed at compile time, or -1 to read it.
+template <int W, int TZ, int TY, int TX, bool QUAD = false, int MODE = -1>
 __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile) {
+  const int mode = MODE >= 0 ? MODE : A.mode;
   using S = GradCubeShape<W, TZ, TY, TX>;
   constexpr int R = S::R;
   constexpr int NT = TZ * TY * TX;
@@ -1251,7 +1253,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
   const int N = n0 * n1 * n2;
   const int z0 = b * TZ, y0 = by * TY, x0 = bx * TX;
   const float si = A.ctl->shift_i, sj = A.ctl->shift_j;
-  if (A.mode == 0 && tile == 0) m_clear(A.ctl, tid);  // M of this iteration
+  if (mode == 0 && tile == 0) m_clear(A.ctl, tid);  // M of this iteration
 
   // the thread's own output voxel: I, J and grad_p I_m, Adam moments
   const int tz = tid / (TY * TX), tr = tid - tz * (TY * TX);
@@ -1273,7 +1275,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
       gather_issue(A.moving_pad, c, gq);
     }
     oI = load_at(A.fixed, ooff) - si;
-    if (A.mode == 0) {
+    if (mode == 0) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         pm[q] = load_at(A.m + q * N, ooff);
@@ -1452,7 +1454,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
     }
     const float dl = -A.inv_n * (oI * SA + oJ * SB - SC);
     const float g[3] = {dl * g0, dl * g1, dl * g2};
-    if (A.mode == 0) {
+    if (mode == 0) {
       const float ibc1 = 1.0f / A.ctl->bc1, ibc2 = 1.0f / A.ctl->bc2;
       const float b1 = A.beta1, b2 = A.beta2;
 #pragma unroll
@@ -1463,7 +1465,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
         store_at(A.v + q * N, ooff, vv);
         store_at(A.out + q * N, ooff, (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps));
       }
-    } else if (A.mode == 1) {
+    } else if (mode == 1) {
       const float gsc = A.gscale ? *A.gscale : 1.0f;
 #pragma unroll
       for (int q = 0; q < 3; ++q) store_at(A.out + q * N, ooff, g[q] * gsc);
@@ -1786,18 +1788,18 @@ __global__ void __launch_bounds__(TY * TX) k_gauss_batch(const BatchEntry<GaussA
   gauss_body<R, TY, TX, EPI>(A, tile, nb);
 }
 
-template <int W, int TZ, int TY, int TX, bool QUAD = false>
+template <int W, int TZ, int TY, int TX, bool QUAD = false, int MODE = -1>
 __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube(const GradArgs A) {
-  grad_cube_body<W, TZ, TY, TX, QUAD>(A, xcd_tile(blockIdx.x, gridDim.x));
+  grad_cube_body<W, TZ, TY, TX, QUAD, MODE>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-template <int W, int TZ, int TY, int TX, bool QUAD = false>
+template <int W, int TZ, int TY, int TX, bool QUAD = false, int MODE = -1>
 __global__ void __launch_bounds__(TZ * TY * TX) k_grad_cube_batch(const BatchEntry<GradArgs>* __restrict__ E,
                                                                   const int* __restrict__ owner) {
   GradArgs A;
   int nb;
   const int tile = batch_entry(E, owner, A, nb);
-  grad_cube_body<W, TZ, TY, TX, QUAD>(A, tile);
+  grad_cube_body<W, TZ, TY, TX, QUAD, MODE>(A, tile);
 }
 
 template <int R, int TZ, int TY, int TX, int EPI>
@@ -2313,24 +2315,25 @@ hipError_t gauss_launch_cube(const GaussArgs& a, int radius, int epi, const Tili
   }
 }
 
-template <int W, bool QUAD>
+template <int W, bool QUAD, int MODE = -1>
 hipError_t grad_cube_wq(const GradArgs& a, const Tiling& t, hipStream_t s) {
   constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
   constexpr size_t sh = GradCubeShape<W, TZ, TY, TX>::lds_bytes;
   static_assert(sh <= 160 * 1024 - 1024, "brick gradient LDS exceeds the 160 KiB of a CU");
   static bool attr_set = false;   // raise the dynamic LDS limit once per process
   if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube<W, TZ, TY, TX, QUAD>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_cube<W, TZ, TY, TX, QUAD, MODE>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  k_grad_cube<W, TZ, TY, TX, QUAD><<<dim3(t.blocks()), dim3(TZ * TY * TX), sh, s>>>(a);
+  k_grad_cube<W, TZ, TY, TX, QUAD, MODE><<<dim3(t.blocks()), dim3(TZ * TY * TX), sh, s>>>(a);
   return hipGetLastError();
 }
 
 template <int W>
 hipError_t grad_cube_w(const GradArgs& a, const Tiling& t, hipStream_t s) {
+  if (a.moving_quad && a.mode == 0) return grad_cube_wq<W, true, 0>(a, t, s);
   return a.moving_quad ? grad_cube_wq<W, true>(a, t, s) : grad_cube_wq<W, false>(a, t, s);
 }
 
@@ -2373,25 +2376,26 @@ hipError_t grad_batch_tile(const BatchEntry<GradArgs>* E, const int* owner, int 
   }
 }
 
-template <int W, bool QUAD>
+template <int W, bool QUAD, int MODE = -1>
 hipError_t grad_cube_batch_wq(const BatchEntry<GradArgs>* E, const int* owner, int total, hipStream_t s) {
   constexpr int TZ = kCubeZ, TY = kCubeY, TX = kCubeX;
   constexpr size_t sh = GradCubeShape<W, TZ, TY, TX>::lds_bytes;
   static bool attr_set = false;   // raise the dynamic LDS limit once per process
   if (!attr_set) {
     const hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_grad_cube_batch<W, TZ, TY, TX, QUAD>),
+        reinterpret_cast<const void*>(&k_grad_cube_batch<W, TZ, TY, TX, QUAD, MODE>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  k_grad_cube_batch<W, TZ, TY, TX, QUAD><<<dim3(total), dim3(TZ * TY * TX), sh, s>>>(E, owner);
+  k_grad_cube_batch<W, TZ, TY, TX, QUAD, MODE><<<dim3(total), dim3(TZ * TY * TX), sh, s>>>(E, owner);
   return hipGetLastError();
 }
 
 template <int W>
-hipError_t grad_cube_batch_w(const BatchEntry<GradArgs>* E, const int* owner, int total, bool quad,
+hipError_t grad_cube_batch_w(const BatchEntry<GradArgs>* E, const int* owner, int total, bool quad, bool adam,
                              hipStream_t s) {
+  if (quad && adam) return grad_cube_batch_wq<W, true, 0>(E, owner, total, s);
   return quad ? grad_cube_batch_wq<W, true>(E, owner, total, s) : grad_cube_batch_wq<W, false>(E, owner, total, s);
 }
 
@@ -2516,9 +2520,9 @@ hipError_t launch_grad_batch(const BatchEntry<GradArgs>* E, const int* owner, in
   if (total <= 0) return hipSuccess;
   if (t.cube) {
     switch (window) {
-      case 1: return grad_cube_batch_w<1>(E, owner, total, quad, s);
-      case 3: return grad_cube_batch_w<3>(E, owner, total, quad, s);
-      case 5: return grad_cube_batch_w<5>(E, owner, total, quad, s);
+      case 1: return grad_cube_batch_w<1>(E, owner, total, quad, adam, s);
+      case 3: return grad_cube_batch_w<3>(E, owner, total, quad, adam, s);
+      case 5: return grad_cube_batch_w<5>(E, owner, total, quad, adam, s);
       default: return hipErrorInvalidValue;
     }
   }
