@@ -51,9 +51,10 @@ fa_status fa_pair_get_step_norm(fa_pair pair, float* m_host);
 fa_status fa_pair_get_level_image(fa_pair pair, int level, int which, float* dev_out, fa_shape* shape);
 
 /* Kernel timing.  While enabled (enable = 1), every iteration records HIP
- * events on the pair's stream around each of its kernels; kind 0 = gradient
- * (warp, LNCC, adjoint, Adam), 1 = smoothed direction and its maximum norm,
- * 2 = composition, 3 = warp smoothing.  fa_pair_get_profile synchronises the stream and
+ * events on the pair's stream around each of its kernels; kind as in
+ * fa_pair_set_tuning: 0 = gradient (warp, LNCC, adjoint, Adam), 1 = smoothed
+ * direction and its maximum norm, 2 = warp smoothing, 3 = composition (the
+ * launches run in the order 0, 1, 3, 2).  fa_pair_get_profile synchronises the stream and
  * returns, for level `level` and kernel `kind`, the summed duration in
  * milliseconds and the number of launches recorded since profiling was last
  * enabled.  Enabling clears the totals. */

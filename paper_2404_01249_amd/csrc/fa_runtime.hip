@@ -240,11 +240,13 @@ fa_status get_event(fa_pair P, hipEvent_t* e) {
 fa_status drain_profile(fa_pair P) {
   if (P->pending.empty()) return FA_OK;
   FA_HIP(hipStreamSynchronize(P->stream));
+  // launch order of an iteration, as kernel kinds (fa_pair_set_tuning's numbering)
+  static const int kind_of_launch[4] = {fa::KIND_GRAD, fa::KIND_SMOOTH_MAX, fa::KIND_COMPOSE, fa::KIND_WARP_SMOOTH};
   for (auto& pe : P->pending) {
     for (int k = 0; k < 4; ++k) {
       float ms = 0.0f;
       FA_HIP(hipEventElapsedTime(&ms, pe.e[k], pe.e[k + 1]));
-      const size_t slot = (size_t)pe.level * 4 + k;
+      const size_t slot = (size_t)pe.level * 4 + kind_of_launch[k];
       if (slot < P->prof_ms.size()) {
         P->prof_ms[slot] += ms;
         P->prof_n[slot] += 1;
