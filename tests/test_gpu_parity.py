@@ -257,6 +257,30 @@ def test_brick_launches_match_streaming_launches(shape, sigma_grad, sigma_warp, 
     assert out[0][2] == out[1][2]
 
 
+@pytest.mark.parametrize("shape", [(21, 37, 45), (13, 17, 33)])
+def test_loss_record_in_either_launch(shape):
+    """The iteration's loss record and step count run in the composition, or in
+    the warp smoothing when that is a brick launch: every mix of brick and
+    streaming forms for the two (the autotuner may pick any) gives bitwise the
+    same loss history, field and step norm."""
+    fixed, moving, _ = make_problem(shape, seed=37)
+    out = []
+    for warp, compose in ((1, 1), (2, 1), (1, 2), (2, 2)):   # 1 streaming, 2 brick
+        pr = new_pair(fixed, moving, eta=0.5, sigma_grad=1.0, sigma_warp=0.5, window=5)
+        fa.fa_pair_set_tuning(pr.handle, 2, 0, 0, 0, warp)      # kind 2: warp smoothing
+        fa.fa_pair_set_tuning(pr.handle, 3, 0, 0, 0, compose)   # kind 3: composition
+        pr.set_schedule([2.0, 1.0], [4, 5])
+        assert pr.tiling(1, 2)[3] == (warp == 2) and pr.tiling(1, 3)[3] == (compose == 2)
+        pr.run()
+        out.append((pr.loss_history(), host(pr.field()), pr.step_norm()))
+        pr.close()
+    assert len(out[0][0]) == 9
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0])
+        assert np.array_equal(out[0][1], o[1])
+        assert out[0][2] == o[2]
+
+
 def test_first_iteration_moves_at_most_eta_over_two():
     fixed, moving, _ = make_problem((21, 37, 45), seed=41)
     pr = new_pair(fixed, moving, eta=0.5, sigma_grad=1.0, sigma_warp=0.0)
