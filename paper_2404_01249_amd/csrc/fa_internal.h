@@ -15,6 +15,15 @@ __device__ __forceinline__ float clamp_med3(float v, float lo, float hi) {
   return __builtin_amdgcn_fmed3f(v, lo, hi);
 }
 
+// Adam's direction m_hat / (sqrt(v_hat) + eps) from the updated moments and
+// the reciprocal bias corrections 1 / (1 - beta^t).  The square root is the
+// hardware's v_sqrt_f32: the correctly rounded sqrtf expands to about 15
+// instructions per component here, and the direction needs no correctly
+// rounded root (eps and the fp32 moments dominate its error).
+__device__ __forceinline__ float adam_direction(float mm, float vv, float ibc1, float ibc2, float eps) {
+  return (mm * ibc1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vv * ibc2) + eps);
+}
+
 // Per-pair control block in device memory.  Kernels of one iteration read
 // and update it so that a whole iteration can be replayed (for example from a
 // captured graph) without host involvement.

@@ -315,7 +315,7 @@ k_inv_dir(const float* __restrict__ d, const float* __restrict__ e, unsigned lon
         const float vv = beta2 * v[ia] + (1.0f - beta2) * g * g;
         m[ia] = mm;
         v[ia] = vv;
-        out[ia] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + adam_eps);
+        out[ia] = fa::adam_direction(mm, vv, ibc1, ibc2, adam_eps);
       }
     }
   }

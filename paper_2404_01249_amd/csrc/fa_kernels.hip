@@ -832,7 +832,7 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
             const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
             store_at(A.m + q * N, off, mm);
             store_at(A.v + q * N, off, vv);
-            store_at(A.out + q * N, off, (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps));
+            store_at(A.out + q * N, off, adam_direction(mm, vv, ibc1, ibc2, A.adam_eps));
           }
           // Adam moments of the next output plane
           mv_ready = zc2 + 1 < z1;
@@ -1148,12 +1148,12 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
         store_at(A.out + N, off, v1);
         store_at(A.out + 2 * N, off, v2);
       } else if (EPI == EPI_MAXNORM) {
-        mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
+        mx = fmaxf(mx, v0 * v0 + v1 * v1 + v2 * v2);
       } else if (EPI == EPI_SMOOTH_MAX) {
         store_at(A.out, off, v0);
         store_at(A.out + N, off, v1);
         store_at(A.out + 2 * N, off, v2);
-        mx = fmaxf(mx, sqrtf(v0 * v0 + v1 * v1 + v2 * v2));
+        mx = fmaxf(mx, v0 * v0 + v1 * v1 + v2 * v2);
       } else if (EPI == EPI_COMPOSE_LDS) {
         // d' = u + d(x + u) from the staged planes zo - 1 .. zo + 1; the
         // cell offset floor(u) is -1 or 0 for |u| <= 1 (u = 1 exactly uses
@@ -1198,7 +1198,7 @@ __device__ __forceinline__ void gauss_body(const GaussArgs& A, const int tile, c
 
   if (EPI == EPI_MAXNORM || EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
-    if (tid == 0) m_raise(A.ctl, bm, blockIdx.x);
+    if (tid == 0) m_raise(A.ctl, sqrtf(bm), blockIdx.x);
   }
 }
 
@@ -1463,7 +1463,7 @@ __device__ __forceinline__ void grad_cube_body(const GradArgs& A, const int tile
         const float vv = b2 * pv[q] + (1.0f - b2) * g[q] * g[q];
         store_at(A.m + q * N, ooff, mm);
         store_at(A.v + q * N, ooff, vv);
-        store_at(A.out + q * N, ooff, (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + A.adam_eps));
+        store_at(A.out + q * N, ooff, adam_direction(mm, vv, ibc1, ibc2, A.adam_eps));
       }
     } else if (mode == 1) {
       const float gsc = A.gscale ? *A.gscale : 1.0f;
@@ -1587,11 +1587,11 @@ __device__ __forceinline__ void gauss_cube_body(const GaussArgs& A, const int ti
     store_at(A.out, off, v0);
     store_at(A.out + N, off, v1);
     store_at(A.out + 2 * N, off, v2);
-    if (EPI == EPI_SMOOTH_MAX) mx = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+    if (EPI == EPI_SMOOTH_MAX) mx = v0 * v0 + v1 * v1 + v2 * v2;
   }
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<NT>(mx, reinterpret_cast<float*>(red));
-    if (tid == 0) m_raise(A.ctl, bm, blockIdx.x);
+    if (tid == 0) m_raise(A.ctl, sqrtf(bm), blockIdx.x);
   }
 }
 
@@ -1871,7 +1871,7 @@ k_eulerian_adam(float* __restrict__ ga, const float* __restrict__ d, float* __re
       const float vv = beta2 * v[iq] + (1.0f - beta2) * out[q] * out[q];
       m[iq] = mm;
       v[iq] = vv;
-      ga[iq] = (mm * ibc1) * __builtin_amdgcn_rcpf(sqrtf(vv * ibc2) + adam_eps);
+      ga[iq] = adam_direction(mm, vv, ibc1, ibc2, adam_eps);
     }
   }
 }
@@ -2008,11 +2008,11 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   if (EPI == EPI_SMOOTH_MAX && xin) {
 #pragma unroll
     for (int o = 0; o < 8; ++o)
-      if (a0 + bo + o < na) mx = fmaxf(mx, sqrtf(v[0][o] * v[0][o] + v[1][o] * v[1][o] + v[2][o] * v[2][o]));
+      if (a0 + bo + o < na) mx = fmaxf(mx, v[0][o] * v[0][o] + v[1][o] * v[1][o] + v[2][o] * v[2][o]);
   }
   if (EPI == EPI_SMOOTH_MAX) {
     const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
-    if (threadIdx.x == 0) m_raise(E.ctl, bm, blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+    if (threadIdx.x == 0) m_raise(E.ctl, sqrtf(bm), blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
   }
 }
 
