@@ -865,9 +865,9 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   if (tid == 0) A.partials[tile] = tot;
 }
 
-template <int W, int TY, int TX, bool PIPE>
+template <int W, int TY, int TX, bool PIPE, bool QUAD = false, int MODE = -1>
 __global__ void __launch_bounds__(TY * TX) k_grad(const GradArgs A) {
-  grad_body<W, TY, TX, PIPE>(A, xcd_tile(blockIdx.x, gridDim.x));
+  grad_body<W, TY, TX, PIPE, QUAD, MODE>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // The same kernel compiled for two workgroups per CU (at most 128 VGPRs);
@@ -1756,13 +1756,13 @@ __device__ __forceinline__ int batch_entry(const BatchEntry<Args>* __restrict__ 
   return g - E[e].first;
 }
 
-template <int W, int TY, int TX>
+template <int W, int TY, int TX, bool QUAD = false, int MODE = -1>
 __global__ void __launch_bounds__(TY * TX) k_grad_batch(const BatchEntry<GradArgs>* __restrict__ E,
                                                         const int* __restrict__ owner) {
   GradArgs A;
   int nb;
   const int tile = batch_entry(E, owner, A, nb);
-  grad_body<W, TY, TX, true>(A, tile);
+  grad_body<W, TY, TX, true, QUAD, MODE>(A, tile);
 }
 
 template <int W, int TY, int TX, bool QUAD = false, int MODE = -1>
@@ -2237,6 +2237,8 @@ hipError_t grad_launch_t(const GradArgs& a, const Tiling& t, hipStream_t s) {
     else k_grad_o4<W, TY, TX, true><<<g, blk, sh, s>>>(a);
   } else {
     if (t.variant == 2) k_grad<W, TY, TX, false><<<g, blk, sh, s>>>(a);
+    else if (a.moving_quad && a.mode == 0) k_grad<W, TY, TX, true, true, 0><<<g, blk, sh, s>>>(a);
+    else if (a.moving_quad) k_grad<W, TY, TX, true, true><<<g, blk, sh, s>>>(a);
     else k_grad<W, TY, TX, true><<<g, blk, sh, s>>>(a);
   }
   return hipGetLastError();
@@ -2358,7 +2360,9 @@ hipError_t grad_batch_t(const BatchEntry<GradArgs>* E, const int* owner, int tot
     else if (quad) k_grad_o4_batch<W, TY, TX, true><<<g, blk, sh, s>>>(E, owner);
     else k_grad_o4_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
   } else {
-    k_grad_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
+    if (quad && adam) k_grad_batch<W, TY, TX, true, 0><<<g, blk, sh, s>>>(E, owner);
+    else if (quad) k_grad_batch<W, TY, TX, true><<<g, blk, sh, s>>>(E, owner);
+    else k_grad_batch<W, TY, TX><<<g, blk, sh, s>>>(E, owner);
   }
   return hipGetLastError();
 }
