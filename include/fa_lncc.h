@@ -36,8 +36,9 @@ typedef struct fa_lncc_s* fa_lncc;   /* opaque; owns its reduction buffers */
 /* Create an evaluator for volumes of `shape` (every dimension >= 2,
  * n0*n1*n2 < 2^29), window w (odd, 1..9) and eps >= 0.  Allocates a copy of
  * the moving image with a two-voxel zero border, (n0+4)(n1+4)(n2+4) floats,
- * plus a few KB of device memory; work is enqueued on `hip_stream`
- * (NULL = null stream). */
+ * the same grid as corner quads (four times that, for volumes whose quad copy
+ * stays below 4 GiB), plus a few KB of device memory; work is enqueued on
+ * `hip_stream` (NULL = null stream). */
 fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_stream, fa_lncc* out);
 
 /* Evaluate at (fixed, moving, d), all device pointers of the evaluator's shape.
@@ -61,8 +62,10 @@ void fa_lncc_destroy(fa_lncc h);
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  It computes exactly what fa_lncc_create(shape, window,
  * cc_eps, hip_stream) followed by fa_lncc_eval(fixed, moving, d, loss_dev,
- * grad_dev, grad_scale_dev) computes (same kernels, same launch shapes, so
- * the same bits), with arguments as documented there.
+ * grad_dev, grad_scale_dev) computes (same arithmetic in the same launch
+ * shapes, so the same bits: the evaluator samples the corner-quad copy and
+ * this call the scalar zero-bordered copy, which give every trilinear sample
+ * the same corner values), with arguments as documented there.
  *
  * It calls no hipMalloc, hipFree or other allocating routine.  Every buffer
  * besides the caller's inputs and outputs (control block, reduction partials,

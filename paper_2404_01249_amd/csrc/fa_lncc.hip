@@ -32,6 +32,7 @@ struct fa_lncc_s {
   double* partials = nullptr;   // one per workgroup of the gradient launch
   double* mean_partials = nullptr;  // kMeanBlocks doubles for the intensity means
   float* moving_pad = nullptr;  // the moving image with a zero border, refreshed per call
+  float* moving_quad = nullptr; // the same as corner quads (NULL where quad_supported fails)
 };
 
 namespace {
@@ -43,6 +44,7 @@ void release(fa_lncc h) {
   if (h->partials) (void)hipFree(h->partials);
   if (h->mean_partials) (void)hipFree(h->mean_partials);
   if (h->moving_pad) (void)hipFree(h->moving_pad);
+  if (h->moving_quad) (void)hipFree(h->moving_quad);
   delete h;
 }
 
@@ -100,6 +102,15 @@ fa_status fa_lncc_create(fa_shape shape, int window, float cc_eps, void* hip_str
     release(h);
     return fail(FA_ENOMEM, "device allocation failed");
   }
+  // the gradient kernel samples the corner quads (two 16-byte loads per
+  // trilinear sample instead of eight 4-byte gathers) where they fit
+  if (fa::quad_supported(shape.n0, shape.n1, shape.n2) &&
+      hipMalloc((void**)&h->moving_quad,
+                (size_t)4 * fa::padded_voxels(shape.n0, shape.n1, shape.n2) * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    release(h);
+    return fail(FA_ENOMEM, "device allocation failed");
+  }
   const hipError_t e = fa::launch_ctl_init(h->ctl, 0.9f, 0.999f, 0, 0, h->stream);
   if (e != hipSuccess) {
     release(h);
@@ -119,9 +130,12 @@ fa_status fa_lncc_eval(fa_lncc h, const float* fixed, const float* moving, const
   FA_HIP(fa::launch_mean(fixed, h->n, h->mean_partials, &h->ctl->shift_i, h->stream));
   FA_HIP(fa::launch_mean(moving, h->n, h->mean_partials, &h->ctl->shift_j, h->stream));
   FA_HIP(fa::launch_pad(moving, h->moving_pad, h->shape.n0, h->shape.n1, h->shape.n2, h->stream));
+  if (h->moving_quad)
+    FA_HIP(fa::launch_pad_quad(h->moving_pad, h->moving_quad, h->shape.n0, h->shape.n1, h->shape.n2, h->stream));
   fa::GradArgs ga{};
   ga.fixed = fixed;
   ga.moving_pad = h->moving_pad;
+  ga.moving_quad = h->moving_quad;
   ga.d = d;
   ga.out = grad_dev;
   ga.gscale = grad_scale_dev;
