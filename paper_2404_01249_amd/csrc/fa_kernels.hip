@@ -20,6 +20,8 @@
 // stencil-and-gather workload bound by HBM bandwidth; there is no dense
 // contraction, so no MFMA.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "fa_internal.h"
 
@@ -162,6 +164,17 @@ __device__ __forceinline__ float tri_grad(const float* __restrict__ f, const Cor
 // Number of grid points of [i - r, i + r] inside [0, n).
 __device__ __forceinline__ float clipped_count(int i, int n, int r) {
   return (float)(min(i + r, n - 1) - max(i - r, 0) + 1);
+}
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, each i a compile-time
+// constant in f's body.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // Box sums of two neighbouring outputs along a row: out[0] = in[0] + ... +
@@ -654,16 +667,36 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
   float pm[3] = {0.f, 0.f, 0.f}, pv[3] = {0.f, 0.f, 0.f};
   bool mv_ready = false;
 
-  for (int zin = zs; zin < ze; ++zin) {
+  // The register rings of I, J (per column) and of the stage-2 sums hold the
+  // last W planes.  Narrow windows rotate them by moves each plane step.  The
+  // wide windows (one workgroup per CU, registers to spare) unroll the march
+  // by W instead: at phase ph of W the newest entry goes to slot ph (slot
+  // (ph + 1) mod W for the stage-2 ring, which starts 2r planes later), so
+  // the j-th oldest entry sits at a slot fixed at compile time and no entry
+  // moves.  The sums still run oldest first; the compiler may form a ring
+  // entry's square or product once for the W windows that hold it instead of
+  // fusing it into each sum, which changes the last bits.
+  constexpr int UNZ = (W >= 7 && TY == 16) ? W : 1;   // not the 8-row tiles of thin volumes
+  auto step = [&](const int zin, auto PH) __attribute__((always_inline)) {
+    constexpr int ph = decltype(PH)::value;
+    constexpr int pha = (ph + 1) % W;
+    // slot of the j-th oldest entry of the I/J rings and of the stage-2 ring
+    auto ri = [](int j) constexpr { return UNZ == 1 ? j : (ph + 1 + j) % W; };
+    auto ra = [](int j) constexpr { return UNZ == 1 ? j : (pha + 1 + j) % W; };
 #pragma unroll
     for (int k = 0; k < CPT1; ++k) {
+      if constexpr (UNZ == 1) {
 #pragma unroll
-      for (int j = 0; j < W - 1; ++j) {
-        ringI[k][j] = ringI[k][j + 1];
-        ringJ[k][j] = ringJ[k][j + 1];
+        for (int j = 0; j < W - 1; ++j) {
+          ringI[k][j] = ringI[k][j + 1];
+          ringJ[k][j] = ringJ[k][j + 1];
+        }
+        ringI[k][W - 1] = curI[k];
+        ringJ[k][W - 1] = curJ[k];
+      } else {
+        ringI[k][ph] = curI[k];
+        ringJ[k][ph] = curJ[k];
       }
-      ringI[k][W - 1] = curI[k];
-      ringJ[k][W - 1] = curJ[k];
     }
     if (R == 0) store_g(zin);
     // next plane: gathers in flight during this plane's passes (PIPE), or
@@ -687,11 +720,11 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
         if (cuse[k]) {
           // sums start from the first term: 0 + x is not foldable in IEEE
           // arithmetic (signed zero) and would cost an add per sum
-          const float i0 = ringI[k][0], j0 = ringJ[k][0];
+          const float i0 = ringI[k][ri(0)], j0 = ringJ[k][ri(0)];
           float s0 = i0, s1 = j0, s2 = i0 * i0, s3 = j0 * j0, s4 = i0 * j0;
 #pragma unroll
           for (int j = 1; j < W; ++j) {
-            const float i_ = ringI[k][j], j_ = ringJ[k][j];
+            const float i_ = ringI[k][ri(j)], j_ = ringJ[k][ri(j)];
             s0 += i_;
             s1 += j_;
             s2 += i_ * i_;
@@ -784,15 +817,21 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
           sb += src[XS2 + k * TX];
           sc += src[2 * XS2 + k * TX];
         }
+        if constexpr (UNZ == 1) {
 #pragma unroll
-        for (int j = 0; j < W - 1; ++j) {
-          ringA[j] = ringA[j + 1];
-          ringB[j] = ringB[j + 1];
-          ringC[j] = ringC[j + 1];
+          for (int j = 0; j < W - 1; ++j) {
+            ringA[j] = ringA[j + 1];
+            ringB[j] = ringB[j + 1];
+            ringC[j] = ringC[j + 1];
+          }
+          ringA[W - 1] = sa;
+          ringB[W - 1] = sb;
+          ringC[W - 1] = sc;
+        } else {
+          ringA[pha] = sa;
+          ringB[pha] = sb;
+          ringC[pha] = sc;
         }
-        ringA[W - 1] = sa;
-        ringB[W - 1] = sb;
-        ringC[W - 1] = sc;
       }
       const int zc2 = zc1 - R;
       if (zc2 >= z0 && out_col) {
@@ -804,15 +843,15 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
             pv[q] = load_at(A.v + q * N, off);
           }
         }
-        float SA = ringA[0], SB = ringB[0], SC = ringC[0];
+        float SA = ringA[ra(0)], SB = ringB[ra(0)], SC = ringC[ra(0)];
 #pragma unroll
         for (int j = 1; j < W; ++j) {
-          SA += ringA[j];
-          SB += ringB[j];
-          SC += ringC[j];
+          SA += ringA[ra(j)];
+          SB += ringB[ra(j)];
+          SC += ringC[ra(j)];
         }
         // oldest ring entries of the own column hold plane zc2
-        const float dl = -A.inv_n * (ringI[0][0] * SA + ringJ[0][0] * SB - SC);
+        const float dl = -A.inv_n * (ringI[0][ri(0)] * SA + ringJ[0][ri(0)] * SB - SC);
         float g[3];
         if constexpr (GLDS) {
           const float* gs = gring + (((zc2 % GS) + GS) % GS) * 3 * NT + tid;
@@ -860,6 +899,16 @@ __device__ __forceinline__ void grad_body(const GradArgs& A, const int tile) {
     }
 #pragma unroll
     for (int k = 0; k < CPT1; ++k) finish_gather(k);
+  };
+  if constexpr (UNZ == 1) {
+    for (int zin = zs; zin < ze; ++zin) step(zin, std::integral_constant<int, 0>{});
+  } else {
+    // the guard is uniform across the workgroup, so the barriers inside
+    // are reached by every thread or by none
+    for (int zb = zs; zb < ze; zb += UNZ)
+      static_for<UNZ>([&](auto PH) __attribute__((always_inline)) {
+        if (zb + decltype(PH)::value < ze) step(zb + decltype(PH)::value, PH);
+      });
   }
   const double tot = block_sum<NT>((double)lacc, red);
   if (tid == 0) A.partials[tile] = tot;
