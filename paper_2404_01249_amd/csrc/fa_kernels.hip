@@ -1995,7 +1995,7 @@ __global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ 
   }
 }
 
-// Along n1 (axis 1) or n0 (axis 0): a workgroup of 64 x 4 threads takes 64
+// Along n1 (axis 1) or n0 (axis 0): a workgroup of 64 x 8 threads takes 64
 // consecutive n2 columns and kWideRun consecutive positions along the axis
 // (grid: ceil(n2/64), ceil(n_axis/kWideRun), the remaining axis); thread
 // (lane, j) forms the 8 consecutive outputs 8j .. 8j+7 of its column from a
@@ -2005,13 +2005,15 @@ __global__ void __launch_bounds__(256) k_field_wide_x(const float* __restrict__ 
 // once per tap.  One component is staged at a time.  The last pass (axis 0)
 // also runs the smoothing's epilogue (EPI): the max norm M of the result
 // (EPI_SMOOTH_MAX), as the streaming kernels do; E carries the control block.
-constexpr int kWideRun = 32;
+// (64 positions: at radius 18 a run of 32 re-read 36 halo positions for
+// every 32 outputs)
+constexpr int kWideRun = 64, kWideThreads = 8 * kWideRun;
 template <int AX, int EPI>
-__global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
+__global__ void __launch_bounds__(kWideThreads) k_field_wide_yz(const float* __restrict__ in, float* __restrict__ out,
                                                        int n0, int n1, int n2, const float* __restrict__ w, int R,
                                                        const GaussArgs E) {
   extern __shared__ float wl[];   // [kWideRun + L8][64], one component at a time
-  __shared__ double red[4];
+  __shared__ double red[kWideThreads / 64];
   const int L8 = (2 * R + 1 + 7) / 8 * 8;
   const int LS = kWideRun + L8;
   const int lane = threadIdx.x & 63, j0 = threadIdx.x >> 6;
@@ -2027,7 +2029,7 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
   float v[3][8];
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();   // the previous component's reads are done
-    for (int i = j0; i < LS; i += 4) {
+    for (int i = j0; i < LS; i += kWideThreads / 64) {
       const int aa = min(max(a0 - R + i, 0), na - 1);
       wl[i * 64 + lane] = xin ? in[c * N + base + aa * astride + x] : 0.0f;
     }
@@ -2060,7 +2062,7 @@ __global__ void __launch_bounds__(256) k_field_wide_yz(const float* __restrict__
       if (a0 + bo + o < na) mx = fmaxf(mx, v[0][o] * v[0][o] + v[1][o] * v[1][o] + v[2][o] * v[2][o]);
   }
   if (EPI == EPI_SMOOTH_MAX) {
-    const float bm = block_max<256>(mx, reinterpret_cast<float*>(red));
+    const float bm = block_max<kWideThreads>(mx, reinterpret_cast<float*>(red));
     if (threadIdx.x == 0) m_raise(E.ctl, sqrtf(bm), blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
   }
 }
@@ -2621,15 +2623,17 @@ hipError_t launch_gauss_wide(const GaussArgs& a, int radius, int epilogue, const
   // one component staged at a time: the run plus the taps rounded up to 8
   const size_t shyz = sizeof(float) * (kWideRun + l8) * 64;
   k_field_wide_x<<<dim3((n2 + 255) / 256, n1, n0), dim3(256), shx, s>>>(a.in, a.out, n0, n1, n2, a.wts, radius);
-  k_field_wide_yz<1, EPI_STORE><<<dim3((n2 + 63) / 64, (n1 + kWideRun - 1) / kWideRun, n0), dim3(256), shyz, s>>>(
+  k_field_wide_yz<1, EPI_STORE><<<dim3((n2 + 63) / 64, (n1 + kWideRun - 1) / kWideRun, n0), dim3(kWideThreads), shyz, s>>>(
       a.out, a.wide_tmp, n0, n1, n2, a.wts, radius, a);
   const dim3 g0((n2 + 63) / 64, (n0 + kWideRun - 1) / kWideRun, n1);
   switch (epilogue) {
     case EPI_SMOOTH_MAX:
-      k_field_wide_yz<0, EPI_SMOOTH_MAX><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
+      k_field_wide_yz<0, EPI_SMOOTH_MAX><<<g0, dim3(kWideThreads), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts,
+                                                                           radius, a);
       break;
     default:
-      k_field_wide_yz<0, EPI_STORE><<<g0, dim3(256), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius, a);
+      k_field_wide_yz<0, EPI_STORE><<<g0, dim3(kWideThreads), shyz, s>>>(a.wide_tmp, a.out, n0, n1, n2, a.wts, radius,
+                                                                      a);
       break;
   }
   return hipGetLastError();
